@@ -1,0 +1,80 @@
+"""The oracle's pins are strong enough: each plausible mistake planted in a
+temporary copy of the oracle source (a dropped term, a wrong sign or index,
+a transposed operand, a wrong time level) makes at least one pin fail.
+
+Mistakes are planted on the CPU, in a copy under pytest's tmp_path; the
+committed oracle is never modified."""
+import os
+
+import pytest
+
+import oracle
+import test_oracle_fct as tf
+import test_oracle_physics as tp
+import test_oracle_recovery as tr
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "shasta_oracle.c")
+
+MUTANTS = {
+    "drop_source": ("has_source ? lam * (-0.5) * (f[P(j + 1)] - f[P(j - 1)]) : 0.0", "0.0"),
+    "source_sign": ("lam * (-0.5) * (f[P(j + 1)]", "lam * (0.5) * (f[P(j + 1)]"),
+    "qminus_denominator_sign": ("(1.0 - (eps[P(j - 1)] - eps[P(j)]))", "(1.0 + (eps[P(j - 1)] - eps[P(j)]))"),
+    "qplus_numerator_sign": ("Qp[P(j)] = (0.5 - eps[P(j)])", "Qp[P(j)] = (0.5 + eps[P(j)])"),
+    "transposed_delta": ("0.5 * Qp[P(j)] * Qp[P(j)] * D[P(j)] -", "0.5 * Qp[P(j)] * Qp[P(j)] * D[P(j - 1)] -"),
+    "qsum_dropped": ("(Qp[P(j)] + Qm[P(j)]) * U[P(j)]", "U[P(j)]"),
+    "antidiffusion_coeff": ("(diff / 8.0)", "(diff / 6.0)"),
+    "second_difference_coeff": ("second / 8.0", "second / 4.0"),
+    "limiter_drops_term": ("fmin(fmin(s * Dh[P(j + 1)], fabs(Aph)), s * Dh[P(j - 1)])", "fmin(s * Dh[P(j + 1)], fabs(Aph))"),
+    "limiter_wrong_neighbour": ("s * Dh[P(j - 1)])", "s * Dh[P(j)])"),
+    "update_sign": ("Uh[P(j)] - (A[P(j)] - A[P(j - 1)])", "Uh[P(j)] - (A[P(j)] + A[P(j - 1)])"),
+    "recovery_uses_E_for_p": ("orc_pressure(eos, e_trial)", "orc_pressure(eos, Ec)"),
+    "recovery_loose_tolerance": ("1125899906842624.0", "1048576.0"),
+    "predictor_full_lambda_velocity": ("eps[i] = (0.5 * lam) * vel[0];", "eps[i] = lam * vel[0];"),
+    "predictor_full_lambda_source": ("src, 0.5 * lam, diff, uh[q] + ORC_HALO", "src, lam, diff, uh[q] + ORC_HALO"),
+    "corrector_from_half_step": ("orc_fct_1d(N, u[q], eps, f, src, lam, diff, out, fl);", "orc_fct_1d(N, uh[q], eps, f, src, lam, diff, out, fl);"),
+    "energy_source_without_v": ("    eps[i] = lam * vel[0];\n    fE[i] = p * vel[0];", "    eps[i] = lam * vel[0];\n    fE[i] = p;"),
+    "narrow_halo": ("for (int g = 1; g <= ORC_HALO; ++g)", "for (int g = 1; g <= 2; ++g)"),
+    "no_half_step_halo": ("for (int q = 0; q < ORC_NF; ++q) orc_fill_halo(N, uh[q]);", ""),
+    "source_on_fixed_momentum": ("const int src = (q == 0) || (q == qpar);\n    double fl[2];", "const int src = (q == 0) || (q == 1);\n    double fl[2];"),
+    "schedule_typo": ("2, 1, 0, 1, 2, 0, 1, 0, 2}", "2, 1, 0, 1, 0, 2, 1, 0, 2}"),
+    "energy_definition": ("E[i] = (e[i] + p * v2) * g2;", "E[i] = (e[i] + p) * g2;"),
+    "velocity_direction": ("*vy = v * My / M;", "*vy = v * Mx / M;"),
+    "bag_mixed_phase": ("if (e < e_Q) return eos->e_H / 3.0;", "if (e < e_Q) return e / 3.0;"),
+}
+
+PINS = [
+    lambda o, ob: tr.test_recovery_ideal_closed_form(o),
+    lambda o, ob: tr.test_recovery_bag_closed_form(ob),
+    lambda o, ob: tr.test_prim_cons_round_trip(o),
+    lambda o, ob: tf.test_phoenical_identity_at_rest(o),
+    lambda o, ob: tf.test_step_at_rest_is_preserved_exactly(o),
+    lambda o, ob: [tf.test_boundary_flux_closes_the_sum(o, s, h) for s in (0, 1) for h in (False, True)],
+    lambda o, ob: [tf.test_passive_scalar_no_new_extrema(o, e) for e in (0.2, -0.2)],
+    lambda o, ob: tp.test_shock_tube_vs_exact(o, 50),
+    lambda o, ob: tp.test_shock_tube_boundary_pressure_flux(o),
+    lambda o, ob: tp.test_planar_invariance_bitwise(o),
+    lambda o, ob: tp.test_conservation_ledger(o),
+    lambda o, ob: tp.test_schedule_is_listing_2_table(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique/present: {name}"
+    path = tmp_path / "mut.c"
+    path.write_text(src.replace(old, new))
+    lib = str(tmp_path / "libmut.so")
+    oracle.build(str(path), lib)
+    from paper_1206_0919_amd import inputs
+    B, e_H = inputs.bag_parameters()
+    o = oracle.Oracle(lib_path=lib)
+    ob = oracle.Oracle(oracle.EOS_BAG, B, e_H, lib_path=lib)
+    caught = []
+    for i, pin in enumerate(PINS):
+        try:
+            pin(o, ob)
+        except (AssertionError, ValueError, FloatingPointError, IndexError):
+            caught.append(i)
+    assert caught, f"mutant {name} passed every pin"
