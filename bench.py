@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the relativistic SHASTA time step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--variants]
+
+A step is one full time step (three directional sweeps and the step
+reductions) of the whole batch, with the state resident in HBM.  Prints one
+JSON line with cell-updates/s, the roofline of the dominant kernel (HIP-event
+timing of each launch on the library's stream, algorithmic bytes per launch)
+and the FP64 CPU oracle timed on a bounded sample on the host cores.
+
+Workloads (synthetic, seeded):
+  hotspots200     200^3, dx 0.2 fm, dt/dx 0.4, p = e/3, 64 Gaussian hot spots,
+                  FP64 (default: the configuration the metric is quoted on)
+  shock256_mixed  256^3 planar shock tube, FP32 fields + FP64 recovery
+  batch96         96 events, axes from {48,64,96,128}, FP32 + FP64 recovery
+  bag400          400^3, dx 0.1 fm, bag-model EOS, FP32 + FP64 recovery
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FIELD_PASSES = 2 * 5           # one read and one write of five fields per sweep
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("shasta_kernels.hip", "shasta_math.hpp", "shasta_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1206_0919_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def make_state(torch, B, wl, precision):
+    dims = wl["dims"] if isinstance(wl["dims"], list) else [wl["dims"]]
+    kind, params = wl["eos"]
+    eos = (B.EOS_BAG, params) if kind == "bag" else None
+    t0 = time.time()
+    prims = wl["init"]()
+    if not isinstance(prims, list):
+        prims = [prims]
+    log(f"initial state generated in {time.time() - t0:.1f}s")
+    s = B.Shasta(dims, wl["dx"], precision=precision, eos=eos)
+    for k, pr in enumerate(prims):
+        s.write_primitive(k, *[torch.from_numpy(a) for a in pr.as_tuple()])
+    cells = sum(d[0] * d[1] * d[2] for d in dims)
+    return s, prims, cells
+
+
+def time_steps(torch, s, dt, steps):
+    st = s.stream
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(st)
+    s.step(dt, steps)
+    b.record(st)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def kernel_profile(torch, s, dt, steps):
+    s.set_profiling(True)
+    s.step(dt, steps)
+    ms, n = s.read_profile()
+    s.set_profiling(False)
+    names = ("sweep_x", "sweep_y", "sweep_z", "step_reduce")
+    return {names[i]: dict(ms_total=ms[i], launches=n[i],
+                           avg_us=1000.0 * ms[i] / n[i] if n[i] else None)
+            for i in range(4)}
+
+
+def cpu_baseline(wl, prims, budget_s=20.0):
+    import numpy as np
+    import oracle
+    kind, params = wl["eos"]
+    o = oracle.Oracle(oracle.EOS_BAG, *params) if kind == "bag" else oracle.Oracle()
+    cores = o.max_threads()
+    pr = prims[0]
+    dims = pr.e.shape[::-1]
+    U = [np.ascontiguousarray(a.reshape(pr.e.shape)) for a in o.prim_to_cons(*pr.as_tuple())]
+    cells = int(np.prod(dims))
+    # one step first, to size the sample to the time budget
+    t0 = time.perf_counter()
+    o.run(U, wl["lam"], 1, k0=0)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(50, int(budget_s / max(t1, 1e-6)) - 1))
+    t0 = time.perf_counter()
+    o.run(U, wl["lam"], n, k0=1)
+    t = time.perf_counter() - t0
+    return dict(value=cells * n / t, unit="cell-updates/s", cores=cores, kind="oracle",
+                sample=f"{wl['name']} event 0 ({dims[0]}x{dims[1]}x{dims[2]}), steps 2..{n + 1} "
+                       f"of the FP64 oracle, OpenMP over pencils, {cores} threads, {t:.1f}s")
+
+
+def run_workload(torch, B, name, steps, warmup, autotune=True, profile_steps=12):
+    from paper_1206_0919_amd import inputs
+    wl = inputs.workload(name)
+    precision = B.FP32_MIXED if wl["precision"] == "fp32" else B.FP64
+    s, prims, cells = make_state(torch, B, wl, precision)
+    dt = wl["lam"] * wl["dx"]
+    if autotune:
+        t0 = time.time()
+        s.autotune(dt, 3)
+        log(f"{name}: autotuned in {time.time() - t0:.1f}s: "
+            + ", ".join(f"axis{a}={s.get_tiles(a)}" for a in range(3)))
+    s.step(dt, warmup)
+    torch.cuda.synchronize()
+    log(f"{name}: warmup {warmup} steps done; timing {steps} steps")
+    ms = time_steps(torch, s, dt, steps)
+    prof = kernel_profile(torch, s, dt, profile_steps)
+    return s, prims, wl, cells, ms, prof, precision
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--workload", default="hotspots200")
+    ap.add_argument("--variants", action="store_true",
+                    help="also measure the FP32 and batched workloads")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(events would shard across GPUs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1206_0919_amd import binding as B
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    s, prims, wl, cells, ms, prof, precision = run_workload(
+        torch, B, args.workload, args.steps, args.warmup, not args.no_autotune)
+    value = cells * args.steps / (ms / 1000.0)
+    esize = 8 if precision == B.FP64 else 4
+    # dominant kernel: the sweep class with the largest total time
+    sweeps = {k: v for k, v in prof.items() if k.startswith("sweep") and v["launches"]}
+    dom = max(sweeps, key=lambda k: sweeps[k]["ms_total"])
+    per_launch = cells * FIELD_PASSES * esize          # algorithmic bytes
+    achieved = per_launch / (sweeps[dom]["avg_us"] * 1e-6) / 1e9
+    traffic = measured_traffic(dom, args.workload)
+    step_bytes = 3 * per_launch
+    rec = {
+        "metric": "SHASTA cell-updates/s per step (FP64 vs FP32 vs batched), % HBM roofline",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == B.FP64 else "f32 fields, f64 recovery",
+        "data": "synthetic",
+        "config": {"workload": wl["name"],
+                   "grid": wl["dims"] if not isinstance(wl["dims"], list) else "96 events",
+                   "cells": cells, "dx_fm": wl["dx"], "dt_over_dx": wl["lam"],
+                   "eos": wl["eos"][0], "precision": wl["precision"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": dom,
+                     "kernel_avg_us": sweeps[dom]["avg_us"],
+                     "bytes_per_launch": per_launch},
+        "step_hbm_frac": value * (step_bytes / cells) / (HBM_PEAK_GBS * 1e9),
+        "kernels": prof,
+    }
+    red = s.reduce(0)
+    rec["check"] = {"nonfinite": red["nonfinite"], "clamp": red["clamp"],
+                    "floor": red["floor"], "max_eps": red["max_eps"]}
+    if args.variants:
+        rec["variants"] = {}
+        for name in ("shock256_mixed", "batch96"):
+            v = run_workload(torch, B, name, max(20, args.steps // 5), args.warmup,
+                             not args.no_autotune)
+            vs, _, vwl, vcells, vms, vprof, vprec = v
+            vsteps = max(20, args.steps // 5)
+            vsw = {k: x for k, x in vprof.items() if k.startswith("sweep") and x["launches"]}
+            vdom = max(vsw, key=lambda k: vsw[k]["ms_total"])
+            vesize = 8 if vprec == B.FP64 else 4
+            vach = vcells * FIELD_PASSES * vesize / (vsw[vdom]["avg_us"] * 1e-6) / 1e9
+            rec["variants"][name] = {
+                "value": vcells * vsteps / (vms / 1000.0), "unit": "cell-updates/s",
+                "ms_per_step": vms / vsteps, "steps": vsteps, "cells": vcells,
+                "dominant_kernel": vdom, "achieved_GBs": vach,
+                "frac": vach / HBM_PEAK_GBS, "kernels": vprof}
+            vs.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        rec["cpu_baseline"] = cpu_baseline(wl, prims)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * shasta.h — C ABI of the MI355X (gfx950) relativistic SHASTA library.
+ *
+ * One time step of the 3+1D relativistic SHASTA flux-corrected transport of
+ * "Relativistic Hydrodynamics on Graphic Cards" (arXiv:1206.0919): the
+ * dimensionally split x/y/z sweeps (half-step predictor, transport with
+ * diffusion, phoenical antidiffusion with flux limiter; Sec. 3, eqs.
+ * shasta-diff, shasta-geo, shasta-n) over the conserved fields E, M_x, M_y,
+ * M_z, R (eqs. cf-density, cf-momentum, cf-energy), and the cell-wise
+ * recovery of e, v, n through the equation of state (Sec. 3, last paragraph).
+ *
+ * Conventions for every call
+ *   - Return value: a status code below; no C++ exception crosses the ABI.
+ *     The message of the last failure is available from shasta_last_error().
+ *   - Pointers named *_dev are device (HBM) pointers of the calling process;
+ *     the caller owns them.  Host pointers are named without suffix.
+ *   - Field arrays are dense, x fastest: index = x + nx*(y + ny*z), FP64.
+ *   - Units: e, p, E, M in GeV/fm^3; n, R in fm^-3; lengths fm; times fm/c.
+ *   - A handle is not thread safe; separate handles are independent.
+ *   - Work is enqueued on the HIP stream given at creation.  Calls documented
+ *     as "asynchronous" return before the GPU work ends; device-side errors
+ *     (non-finite results) are reported by the next synchronizing call.
+ */
+#ifndef SHASTA_H
+#define SHASTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shasta_handle shasta_t;
+
+/* status codes */
+#define SHASTA_OK 0
+#define SHASTA_EINVAL 1      /* bad argument (checked on the host)          */
+#define SHASTA_ESTATE 2      /* call out of order (e.g. step before init)   */
+#define SHASTA_EWORKSPACE 3  /* workspace missing, too small or misaligned  */
+#define SHASTA_EHIP 4        /* a HIP runtime call failed                   */
+#define SHASTA_ENONFINITE 5  /* a non-finite value appeared in the fields   */
+#define SHASTA_ENOCONVERGE 6 /* recovery root solve did not converge        */
+
+/* precision of the stored fields and of the transport */
+#define SHASTA_FP64 0       /* everything in FP64                             */
+#define SHASTA_FP32_MIXED 1 /* fields and transport FP32; recovery and sums
+                               FP64 (Sec. 5: double precision for the boost) */
+
+/* boundary condition */
+#define SHASTA_BC_OUTFLOW 0 /* three halo cells copy the edge cell (Sec. 3.1) */
+
+/* equations of state */
+#define SHASTA_EOS_IDEAL 0 /* p = e/3 (Sec. 2, ideal gas)                    */
+#define SHASTA_EOS_BAG 1   /* bag model: p = e/3 (e <= e_H), e_H/3 in the
+                              mixed phase, (e - 4B)/3 (e >= e_H + 4B)        */
+
+/* field indices for shasta_read_field */
+#define SHASTA_FIELD_E 0
+#define SHASTA_FIELD_MX 1
+#define SHASTA_FIELD_MY 2
+#define SHASTA_FIELD_MZ 3
+#define SHASTA_FIELD_R 4
+#define SHASTA_FIELD_e 5  /* recomputed primitives (recovery of Sec. 3) */
+#define SHASTA_FIELD_p 6
+#define SHASTA_FIELD_vx 7
+#define SHASTA_FIELD_vy 8
+#define SHASTA_FIELD_vz 9
+#define SHASTA_FIELD_n 10
+
+/*
+ * Create a handle for a batch of n_events independent grids (a single grid
+ * is a batch of 1).  dims[3*k+0..2] = nx, ny, nz of event k, each >= 1, at
+ * most 2^31-1 cells per event; dx_fm > 0 is the cell size of every event;
+ * precision is SHASTA_FP64 or SHASTA_FP32_MIXED; bc must be
+ * SHASTA_BC_OUTFLOW; hip_stream is a hipStream_t (NULL = default stream).
+ * Validation is done on the CPU before any HIP call; nothing is allocated on
+ * the device.  The EOS defaults to SHASTA_EOS_IDEAL.
+ */
+int shasta_create(shasta_t** out, int n_events, const int32_t* dims,
+                  double dx_fm, int precision, int bc, void* hip_stream);
+
+/* Device bytes the handle needs: ping-pong field buffers, work tables,
+ * reduction records and per-event accumulators. */
+int shasta_workspace_bytes(const shasta_t* h, size_t* bytes);
+
+/* Bind caller-owned device memory (e.g. a torch uint8 tensor), 256-byte
+ * aligned and at least shasta_workspace_bytes() long.  The caller keeps it
+ * alive until shasta_destroy().  Uploads the work tables (synchronous). */
+int shasta_bind_workspace(shasta_t* h, void* dev_ptr, size_t bytes);
+
+/* Select the EOS.  SHASTA_EOS_IDEAL takes no parameters (n_params = 0);
+ * SHASTA_EOS_BAG takes params = {B, e_H} in GeV/fm^3, both > 0 and finite
+ * (e_Q = e_H + 4B is derived). */
+int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params);
+
+/* Write the state of event ev from primitive fields (device pointers to
+ * dense FP64 arrays of the event's cells): e >= 0, |v| < 1, n >= 0.
+ * Converts with eqs. cf-density, cf-momentum, cf-energy on the device.
+ * Synchronous; returns SHASTA_EINVAL (state written anyway) if any cell
+ * violates the ranges.  Resets the accumulators (ledger, t, counters) of ev. */
+int shasta_write_primitive(shasta_t* h, int ev, const double* e_dev,
+                           const double* vx_dev, const double* vy_dev,
+                           const double* vz_dev, const double* n_dev);
+
+/* Write the conserved state of event ev (device FP64 arrays).  Used for
+ * resume; no admissibility check (the recovery guard handles E <= 0 or
+ * |M| >= E and counts it).  Synchronous.  Does not reset the accumulators. */
+int shasta_write_conserved(shasta_t* h, int ev, const double* E_dev,
+                           const double* Mx_dev, const double* My_dev,
+                           const double* Mz_dev, const double* R_dev);
+
+/* Set the step index k; it fixes the axis order of the next step
+ * (Appendix A, Listing 2 permutation table, period 6).  k >= 0. */
+int shasta_set_step_index(shasta_t* h, int64_t k);
+int shasta_get_step_index(const shasta_t* h, int64_t* k);
+
+/*
+ * Advance every event by nsteps >= 0 time steps of dt_fm.  One step = three
+ * directional sweeps with the full dt in the order of the permutation table;
+ * each sweep = outflow halo, recovery at U^n, lambda/2 predictor, recovery at
+ * U^{n+1/2}, lambda corrector from U^n (Sec. 3 and Sec. 3.1).  Requires
+ * 0 < dt/dx < 1/2, a bound workspace and every event written.
+ * Asynchronous on the stream.
+ */
+int shasta_step(shasta_t* h, double dt_fm, int nsteps);
+
+/* Copy one field of event ev to dst_dev (dense FP64, the event's cells).
+ * field 0..4: E, M_x, M_y, M_z, R; 5..10: e, p, v_x, v_y, v_z, n recomputed
+ * from the conserved state.  Synchronizes; returns SHASTA_ENONFINITE if a
+ * non-finite value was flagged since the last write. */
+int shasta_read_field(shasta_t* h, int ev, int field, double* dst_dev);
+
+/*
+ * Reductions of event ev (synchronizes).  out[0..4]: FP64 sums over the
+ * cells of E, M_x, M_y, M_z, R after the last step; out[5..9]: accumulated
+ * net boundary outflow of the same fields since the last write_primitive
+ * (sum(t) + outflow = sum(0) is the conservation invariant); out[10]: largest
+ * |lambda v_sweep| seen; out[11]: elapsed time t.  counters[0..3]: recoveries
+ * with |M| clamped, with E floored, root solves not converged (always 0: the
+ * device root solve is closed form), steps with non-finite values.
+ * Sums are deterministic (fixed reduction order).
+ */
+int shasta_reduce(shasta_t* h, int ev, double out[12], int64_t counters[4]);
+
+int shasta_destroy(shasta_t* h);
+const char* shasta_last_error(const shasta_t* h);
+const char* shasta_status_str(int status);
+
+/* ---------------------------------------------------------------- tuning */
+
+/*
+ * Work decomposition of the sweeps (results are bitwise independent of it).
+ * axis 0 (x sweep): p0 = 4-cell windows per wave (>= 1).  axis 1, 2 (y, z
+ * sweeps): p0 = segment length along the sweep axis (>= 1; the pencil is cut
+ * into ceil(N/p0) segments, each recomputing a 6-cell margin), p1 = lanes
+ * along x per wave (16, 32 or 64).  Rebuilds the work tables; if a workspace
+ * is bound it must still be large enough (shasta_workspace_bytes tells).
+ */
+int shasta_set_tiles(shasta_t* h, int axis, int p0, int p1);
+int shasta_get_tiles(const shasta_t* h, int axis, int* p0, int* p1);
+
+/* Time candidate decompositions on the device with the given dt (state is
+ * saved and restored), keep the fastest per axis.  Synchronous. */
+int shasta_autotune(shasta_t* h, double dt_fm, int reps);
+
+/* Capture the steady-state step cycle (6 steps) in a HIP graph and replay it
+ * (enable = 1, default) or launch kernels one by one (enable = 0). */
+int shasta_set_graph(shasta_t* h, int enable);
+
+/* Per-kernel timing with HIP events on the handle's stream.  While enabled,
+ * shasta_step launches kernel by kernel and records an event pair around
+ * each sweep and reduction launch.  shasta_read_profile synchronizes and
+ * returns the summed milliseconds and launch counts of: [0] x sweeps,
+ * [1] y sweeps, [2] z sweeps, [3] step reductions, then clears them. */
+int shasta_set_profiling(shasta_t* h, int enable);
+int shasta_read_profile(shasta_t* h, double ms[4], int64_t launches[4]);
+
+/* ----------------------------------------------------- measurement helpers */
+
+/* Plain streaming copy of `bytes` (multiple of 16) from src_dev to dst_dev
+ * on hip_stream, used to calibrate bandwidth and traffic counters. */
+int shasta_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
+                       void* hip_stream);
+
+/* Device math self-check: out_dev[i] = f(in_dev[i]) for n values with
+ * which = 0: the FP64 reciprocal, 1: the FP64 square root used by the
+ * kernels.  Synchronous. */
+int shasta_selftest_math(const double* in_dev, double* out_dev, int n,
+                         int which, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHASTA_H */

@@ -1,0 +1,824 @@
+// Host side of the C ABI declared in include/shasta.h: argument validation,
+// device workspace layout, work tables, the time-step schedule (axis
+// permutation cycle of Listing 2, ping-pong buffers), HIP-graph replay,
+// per-kernel event timing and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "shasta.h"
+#include "shasta_internal.hpp"
+
+using namespace shasta;
+
+namespace shasta_launch {
+hipError_t sweep(int fp32, int axis, const void* args, hipStream_t st);
+hipError_t finalize(const EventDesc* ev, int n_events, const double* const rec[3],
+                    const int axis[3], double* acc, double dt, hipStream_t st);
+hipError_t write_prim(int fp32, EosParams eos, const double* e, const double* vx,
+                      const double* vy, const double* vz, const double* n, void* out,
+                      int64_t pitch, int64_t ncell, double* invalid, hipStream_t st);
+hipError_t write_cons(int fp32, const double* E, const double* Mx, const double* My,
+                      const double* Mz, const double* R, void* out, int64_t pitch,
+                      int64_t ncell, hipStream_t st);
+hipError_t read(int fp32, EosParams eos, const void* in, int64_t pitch, int64_t ncell,
+                int field, double* dst, hipStream_t st);
+hipError_t zero(double* p, int64_t n, hipStream_t st);
+hipError_t copy(const void* s, void* d, size_t bytes, hipStream_t st);
+hipError_t selftest(const double* in, double* out, int n, int which, hipStream_t st);
+hipError_t sums(int fp32, const void* in, int64_t pitch, int64_t ncell, double* scratch,
+                double* out, hipStream_t st);
+int sum_scratch_doubles();
+size_t sweep_args_size();
+}  // namespace shasta_launch
+
+namespace {
+
+// Kernel arguments of one sweep; must match SweepArgs in the kernels.
+struct SweepArgsHost {
+  const EventDesc* ev;
+  const Item* items;
+  int n_items;
+  int parity;
+  void* field_base;
+  double lam;
+  double diff;
+  double* rec;
+  EosParams eos;
+};
+
+// Axis order of step k: the permutation table of Listing 2.
+const int kBranch[18] = {0, 1, 2, 0, 2, 1, 2, 0, 1, 2, 1, 0, 1, 2, 0, 1, 0, 2};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct shasta_handle {
+  int n_events = 0;
+  std::vector<int> dims;  // 3 per event
+  double dx = 0.0;
+  int precision = 0;
+  int bc = 0;
+  hipStream_t stream = nullptr;
+  EosParams eos{0, 0, 0.0, 0.0};
+  double diff = 1.0;
+
+  // decomposition (0 = automatic per event)
+  int xwin = 0;
+  int seg[3] = {0, 0, 0};
+  int lanes[3] = {0, 0, 0};
+
+  // tables
+  std::vector<EventDesc> evd;
+  std::vector<Item> items[3];
+  int n_records[3] = {0, 0, 0};
+  int64_t item_cap[3] = {0, 0, 0};
+  int64_t rec_cap = 0;
+
+  // workspace layout
+  size_t elem = 8;
+  size_t field_bytes = 0, off_ev = 0, off_items[3] = {0, 0, 0}, off_rec = 0,
+         off_acc = 0, off_scratch = 0, total = 0;
+  char* ws = nullptr;
+  size_t ws_len = 0;
+
+  std::vector<char> written;
+  int64_t step_index = 0;
+  int parity = 0;
+
+  // graph
+  bool graph_enabled = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double graph_dt = -1.0;
+  int graph_parity = -1;
+  int tables_version = 0, graph_version = -1;
+
+  // profiling
+  bool profiling = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_n[4] = {0, 0, 0, 0};
+
+  std::string err;
+};
+
+namespace {
+
+int fail(shasta_t* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hipfail(shasta_t* h, hipError_t e, const char* where) {
+  return fail(h, SHASTA_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHECK(h, call)                                 \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hipfail((h), e_, #call); \
+  } while (0)
+
+int64_t ncell_of(const shasta_t* h, int ev) {
+  return (int64_t)h->dims[3 * ev] * h->dims[3 * ev + 1] * h->dims[3 * ev + 2];
+}
+
+// lanes along x for a y/z sweep of an event: least padding, ties to more lanes
+int auto_lanes(int nx, int nb) {
+  int best = 64;
+  double best_waste = 1e300;
+  for (int lx : {64, 32, 16}) {
+    const int lb = 64 / lx;
+    const double cells = double((nx + lx - 1) / lx) * lx * double((nb + lb - 1) / lb) * lb;
+    const double waste = cells / (double(nx) * nb);
+    if (waste < best_waste - 1e-12) {
+      best_waste = waste;
+      best = lx;
+    }
+  }
+  return best;
+}
+
+int lanes_for(const shasta_t* h, int axis, int ev) {
+  const int nx = h->dims[3 * ev];
+  const int nb = (axis == 1) ? h->dims[3 * ev + 2] : h->dims[3 * ev + 1];
+  return h->lanes[axis] ? h->lanes[axis] : auto_lanes(nx, nb);
+}
+
+int64_t columns(const shasta_t* h, int axis, int ev, int lx) {
+  const int nx = h->dims[3 * ev];
+  const int nb = (axis == 1) ? h->dims[3 * ev + 2] : h->dims[3 * ev + 1];
+  const int lb = 64 / lx;
+  return (int64_t)((nx + lx - 1) / lx) * ((nb + lb - 1) / lb);
+}
+
+// Build the per-axis work lists.  Every event's list is padded to a whole
+// number of blocks so a block never mixes events.
+void build_tables(shasta_t* h) {
+  const int ne = h->n_events;
+  // total waves of full pencils, used by the automatic segment length
+  int64_t waves_full[3] = {0, 0, 0};
+  for (int ax = 1; ax < 3; ++ax)
+    for (int e = 0; e < ne; ++e) waves_full[ax] += columns(h, ax, e, lanes_for(h, ax, e));
+  const int64_t target_waves = 2048;  // 2 waves on each of 1024 SIMDs
+  for (int ax = 0; ax < 3; ++ax) h->items[ax].clear();
+  int64_t total_windows = 0;
+  for (int e = 0; e < ne; ++e) total_windows += (ncell_of(h, e) + kXOut - 1) / kXOut;
+  int auto_xwin = (int)std::max<int64_t>(1, total_windows / 4096);
+  for (int ax = 0; ax < 3; ++ax) {
+    int rec = 0;
+    for (int e = 0; e < ne; ++e) {
+      EventDesc& d = h->evd[e];
+      const size_t start = h->items[ax].size();
+      if (ax == 0) {
+        const int64_t nc = ncell_of(h, e);
+        const int64_t nwin = (nc + kXOut - 1) / kXOut;
+        const int per = h->xwin ? h->xwin : auto_xwin;
+        for (int64_t w = 0; w < nwin; w += per) {
+          Item it{};
+          it.ev = e;
+          it.a = (int32_t)(w * kXOut);
+          it.b = (int32_t)std::min<int64_t>(per, nwin - w);
+          h->items[ax].push_back(it);
+        }
+      } else {
+        const int N = h->dims[3 * e + ax];
+        const int nx = h->dims[3 * e];
+        const int nb = (ax == 1) ? h->dims[3 * e + 2] : h->dims[3 * e + 1];
+        const int lx = lanes_for(h, ax, e);
+        const int lb = 64 / lx;
+        int L = h->seg[ax];
+        if (L <= 0) {
+          const int64_t nseg = std::max<int64_t>(
+              1, (target_waves + waves_full[ax] - 1) / std::max<int64_t>(1, waves_full[ax]));
+          L = (int)std::max<int64_t>(16, (N + nseg - 1) / nseg);
+        }
+        L = std::min(L, N);
+        for (int b0 = 0; b0 < nb; b0 += lb)
+          for (int x0 = 0; x0 < nx; x0 += lx)
+            for (int s0 = 0; s0 < N; s0 += L) {
+              Item it{};
+              it.ev = e;
+              it.a = x0;
+              it.b = b0;
+              it.s0 = s0;
+              it.s1 = std::min(N, s0 + L);
+              it.lx = lx;
+              h->items[ax].push_back(it);
+            }
+      }
+      while ((h->items[ax].size() - start) % kWavesPerBlock) {
+        Item pad{};
+        pad.ev = -1;
+        pad.lx = 64;
+        h->items[ax].push_back(pad);
+      }
+      d.rec_begin[ax] = rec;
+      d.rec_count[ax] = (int32_t)((h->items[ax].size() - start) / kWavesPerBlock);
+      rec += d.rec_count[ax];
+    }
+    h->n_records[ax] = rec;
+  }
+  h->tables_version++;
+}
+
+// Capacity of the tables over every decomposition the tuner may choose
+// (smallest segment 16, one window per wave), so retuning never needs a
+// larger workspace than the one computed at creation.
+void table_capacity(const shasta_t* h, int64_t cap[3], int64_t& rec_cap) {
+  rec_cap = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    int64_t n = 0;
+    for (int e = 0; e < h->n_events; ++e) {
+      int64_t m;
+      if (ax == 0) {
+        m = (ncell_of(h, e) + kXOut - 1) / kXOut;
+      } else {
+        const int N = h->dims[3 * e + ax];
+        int64_t worst = 0;
+        for (int lx : {16, 32, 64}) worst = std::max(worst, columns(h, ax, e, lx));
+        m = worst * ((N + 15) / 16);
+      }
+      n += (m + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
+    }
+    cap[ax] = n;
+    rec_cap = std::max(rec_cap, n / kWavesPerBlock);
+  }
+}
+
+void layout(shasta_t* h) {
+  h->elem = h->precision == SHASTA_FP32_MIXED ? 4 : 8;
+  h->evd.assign(h->n_events, EventDesc{});
+  int64_t off = 0;  // elements from the field base
+  for (int e = 0; e < h->n_events; ++e) {
+    EventDesc& d = h->evd[e];
+    d.n[0] = h->dims[3 * e];
+    d.n[1] = h->dims[3 * e + 1];
+    d.n[2] = h->dims[3 * e + 2];
+    d.ncell = ncell_of(h, e);
+    d.pitch = (d.ncell + 63) / 64 * 64;  // 256/512-byte aligned field arrays
+    d.off[0] = off;
+    off += kNF * d.pitch;
+    d.off[1] = off;
+    off += kNF * d.pitch;
+  }
+  h->field_bytes = align256((size_t)off * h->elem);
+  table_capacity(h, h->item_cap, h->rec_cap);
+  size_t p = h->field_bytes;
+  h->off_ev = p;
+  p = align256(p + sizeof(EventDesc) * h->n_events);
+  for (int ax = 0; ax < 3; ++ax) {
+    h->off_items[ax] = p;
+    p = align256(p + sizeof(Item) * (size_t)h->item_cap[ax]);
+  }
+  h->off_rec = p;
+  p = align256(p + 3 * sizeof(double) * R_SIZE * (size_t)h->rec_cap);
+  h->off_acc = p;
+  p = align256(p + sizeof(double) * A_SIZE * h->n_events);
+  h->off_scratch = p;
+  p = align256(p + sizeof(double) * shasta_launch::sum_scratch_doubles());
+  h->total = p;
+}
+
+EventDesc* dev_events(shasta_t* h) { return reinterpret_cast<EventDesc*>(h->ws + h->off_ev); }
+Item* dev_items(shasta_t* h, int ax) { return reinterpret_cast<Item*>(h->ws + h->off_items[ax]); }
+double* dev_rec(shasta_t* h, int slot) {
+  return reinterpret_cast<double*>(h->ws + h->off_rec) + (size_t)slot * R_SIZE * h->rec_cap;
+}
+double* dev_acc(shasta_t* h, int ev) {
+  return reinterpret_cast<double*>(h->ws + h->off_acc) + (size_t)ev * A_SIZE;
+}
+char* dev_field(shasta_t* h, int ev, int buf) {
+  return h->ws + (size_t)h->evd[ev].off[buf] * h->elem;
+}
+
+int upload_tables(shasta_t* h) {
+  for (int ax = 0; ax < 3; ++ax)
+    if ((int64_t)h->items[ax].size() > h->item_cap[ax])
+      return fail(h, SHASTA_EWORKSPACE, "work table exceeds the workspace capacity");
+  HIPCHECK(h, hipMemcpyAsync(dev_events(h), h->evd.data(), sizeof(EventDesc) * h->n_events,
+                             hipMemcpyHostToDevice, h->stream));
+  for (int ax = 0; ax < 3; ++ax)
+    HIPCHECK(h, hipMemcpyAsync(dev_items(h, ax), h->items[ax].data(),
+                               sizeof(Item) * h->items[ax].size(), hipMemcpyHostToDevice,
+                               h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return SHASTA_OK;
+}
+
+void drop_graph(shasta_t* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->graph_version = -1;
+}
+
+hipEvent_t take_event(shasta_t* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStream_t st) {
+  SweepArgsHost a;
+  a.ev = dev_events(h);
+  a.items = dev_items(h, axis);
+  a.n_items = (int)h->items[axis].size();
+  a.parity = parity;
+  a.field_base = h->ws;
+  a.lam = lam;
+  a.diff = h->diff;
+  a.rec = dev_rec(h, slot);
+  a.eos = h->eos;
+  if (a.n_items == 0) return SHASTA_OK;
+  const bool prof = h->profiling && st == h->stream;
+  ProfRec pr{axis, nullptr, nullptr};
+  if (prof) {
+    pr.a = take_event(h);
+    pr.b = take_event(h);
+    if (!pr.a || !pr.b) return fail(h, SHASTA_EHIP, "hipEventCreate failed");
+    HIPCHECK(h, hipEventRecord(pr.a, st));
+  }
+  HIPCHECK(h, shasta_launch::sweep(h->precision == SHASTA_FP32_MIXED, axis, &a, st));
+  if (prof) {
+    HIPCHECK(h, hipEventRecord(pr.b, st));
+    h->prof.push_back(pr);
+  }
+  return SHASTA_OK;
+}
+
+// One time step (three sweeps and the step reduction) enqueued on st.
+int enqueue_step(shasta_t* h, int64_t k, int& parity, double dt, hipStream_t st) {
+  const double lam = dt / h->dx;
+  const int* perm = &kBranch[3 * (int)(k % 6)];
+  for (int w = 0; w < 3; ++w) {
+    int rc = launch_sweep(h, perm[w], parity, w, lam, st);
+    if (rc) return rc;
+    parity ^= 1;
+  }
+  const double* rec[3] = {dev_rec(h, 0), dev_rec(h, 1), dev_rec(h, 2)};
+  const bool prof = h->profiling && st == h->stream;
+  ProfRec pr{3, nullptr, nullptr};
+  if (prof) {
+    pr.a = take_event(h);
+    pr.b = take_event(h);
+    if (!pr.a || !pr.b) return fail(h, SHASTA_EHIP, "hipEventCreate failed");
+    HIPCHECK(h, hipEventRecord(pr.a, st));
+  }
+  HIPCHECK(h, shasta_launch::finalize(dev_events(h), h->n_events, rec, perm, dev_acc(h, 0),
+                                      dt, st));
+  if (prof) {
+    HIPCHECK(h, hipEventRecord(pr.b, st));
+    h->prof.push_back(pr);
+  }
+  return SHASTA_OK;
+}
+
+int capture_cycle(shasta_t* h, double dt) {
+  drop_graph(h);
+  if (!h->cap_stream)
+    HIPCHECK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIPCHECK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int parity = h->parity;
+  int rc = SHASTA_OK;
+  for (int s = 0; s < 6 && rc == SHASTA_OK; ++s) rc = enqueue_step(h, s, parity, dt, h->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hipfail(h, e, "hipStreamEndCapture");
+  h->graph = g;
+  HIPCHECK(h, hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  h->graph_dt = dt;
+  h->graph_parity = h->parity;
+  h->graph_version = h->tables_version;
+  return SHASTA_OK;
+}
+
+int check_ready(shasta_t* h) {
+  if (!h->ws) return fail(h, SHASTA_ESTATE, "no workspace bound");
+  for (int e = 0; e < h->n_events; ++e)
+    if (!h->written[e]) return fail(h, SHASTA_ESTATE, "event " + std::to_string(e) + " not written");
+  return SHASTA_OK;
+}
+
+int check_event(shasta_t* h, int ev) {
+  if (ev < 0 || ev >= h->n_events) return fail(h, SHASTA_EINVAL, "event index out of range");
+  return SHASTA_OK;
+}
+
+int read_acc(shasta_t* h, int ev, double* a) {
+  HIPCHECK(h, hipMemcpyAsync(a, dev_acc(h, ev), sizeof(double) * A_SIZE,
+                             hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return SHASTA_OK;
+}
+
+int refresh_sums(shasta_t* h, int ev) {
+  const EventDesc& d = h->evd[ev];
+  HIPCHECK(h, shasta_launch::sums(h->precision == SHASTA_FP32_MIXED, dev_field(h, ev, h->parity),
+                                  d.pitch, d.ncell,
+                                  reinterpret_cast<double*>(h->ws + h->off_scratch),
+                                  dev_acc(h, ev) + A_SUM, h->stream));
+  return SHASTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int shasta_create(shasta_t** out, int n_events, const int32_t* dims, double dx_fm,
+                  int precision, int bc, void* hip_stream) {
+  if (!out) return SHASTA_EINVAL;
+  *out = nullptr;
+  if (n_events < 1 || !dims) return SHASTA_EINVAL;
+  if (!(dx_fm > 0.0) || !std::isfinite(dx_fm)) return SHASTA_EINVAL;
+  if (precision != SHASTA_FP64 && precision != SHASTA_FP32_MIXED) return SHASTA_EINVAL;
+  if (bc != SHASTA_BC_OUTFLOW) return SHASTA_EINVAL;
+  for (int e = 0; e < n_events; ++e) {
+    int64_t c = 1;
+    for (int a = 0; a < 3; ++a) {
+      if (dims[3 * e + a] < 1) return SHASTA_EINVAL;
+      c *= dims[3 * e + a];
+    }
+    if (c > 2147483647LL - 4096) return SHASTA_EINVAL;
+  }
+  shasta_t* h = new (std::nothrow) shasta_t();
+  if (!h) return SHASTA_EINVAL;
+  h->n_events = n_events;
+  h->dims.assign(dims, dims + 3 * n_events);
+  h->dx = dx_fm;
+  h->precision = precision;
+  h->bc = bc;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->written.assign(n_events, 0);
+  layout(h);
+  build_tables(h);
+  *out = h;
+  return SHASTA_OK;
+}
+
+int shasta_workspace_bytes(const shasta_t* h, size_t* bytes) {
+  if (!h || !bytes) return SHASTA_EINVAL;
+  *bytes = h->total;
+  return SHASTA_OK;
+}
+
+int shasta_bind_workspace(shasta_t* h, void* dev_ptr, size_t bytes) {
+  if (!h) return SHASTA_EINVAL;
+  if (!dev_ptr) return fail(h, SHASTA_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 256)
+    return fail(h, SHASTA_EWORKSPACE, "workspace not 256-byte aligned");
+  if (bytes < h->total)
+    return fail(h, SHASTA_EWORKSPACE, "workspace too small: need " + std::to_string(h->total));
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(h, SHASTA_EWORKSPACE, "workspace is not device memory");
+  }
+  drop_graph(h);
+  h->ws = static_cast<char*>(dev_ptr);
+  h->ws_len = bytes;
+  h->written.assign(h->n_events, 0);
+  h->parity = 0;
+  int rc = upload_tables(h);
+  if (rc) return rc;
+  HIPCHECK(h, shasta_launch::zero(dev_acc(h, 0), (int64_t)A_SIZE * h->n_events, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  return SHASTA_OK;
+}
+
+int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params) {
+  if (!h) return SHASTA_EINVAL;
+  if (kind == SHASTA_EOS_IDEAL) {
+    if (n_params != 0) return fail(h, SHASTA_EINVAL, "ideal EOS takes no parameters");
+    h->eos = EosParams{0, 0, 0.0, 0.0};
+  } else if (kind == SHASTA_EOS_BAG) {
+    if (n_params != 2 || !params) return fail(h, SHASTA_EINVAL, "bag EOS takes {B, e_H}");
+    const double B = params[0], eH = params[1];
+    if (!(B > 0.0) || !(eH > 0.0) || !std::isfinite(B) || !std::isfinite(eH))
+      return fail(h, SHASTA_EINVAL, "bag EOS needs B > 0 and e_H > 0");
+    h->eos = EosParams{1, 0, B, eH};
+  } else {
+    return fail(h, SHASTA_EINVAL, "unknown EOS kind");
+  }
+  drop_graph(h);
+  return SHASTA_OK;
+}
+
+int shasta_write_primitive(shasta_t* h, int ev, const double* e, const double* vx,
+                           const double* vy, const double* vz, const double* n) {
+  if (!h) return SHASTA_EINVAL;
+  if (int rc = check_event(h, ev)) return rc;
+  if (!h->ws) return fail(h, SHASTA_ESTATE, "no workspace bound");
+  if (!e || !vx || !vy || !vz || !n) return fail(h, SHASTA_EINVAL, "null field pointer");
+  const EventDesc& d = h->evd[ev];
+  double* acc = dev_acc(h, ev);
+  HIPCHECK(h, shasta_launch::zero(acc, A_SIZE, h->stream));
+  HIPCHECK(h, shasta_launch::write_prim(h->precision == SHASTA_FP32_MIXED, h->eos, e, vx, vy, vz,
+                                        n, dev_field(h, ev, h->parity), d.pitch, d.ncell,
+                                        acc + A_INVALID, h->stream));
+  if (int rc = refresh_sums(h, ev)) return rc;
+  double a[A_SIZE];
+  if (int rc = read_acc(h, ev, a)) return rc;
+  h->written[ev] = 1;
+  if (a[A_INVALID] > 0)
+    return fail(h, SHASTA_EINVAL, std::to_string((long long)a[A_INVALID]) +
+                                      " cells violate e >= 0, |v| < 1, n >= 0");
+  return SHASTA_OK;
+}
+
+int shasta_write_conserved(shasta_t* h, int ev, const double* E, const double* Mx,
+                           const double* My, const double* Mz, const double* R) {
+  if (!h) return SHASTA_EINVAL;
+  if (int rc = check_event(h, ev)) return rc;
+  if (!h->ws) return fail(h, SHASTA_ESTATE, "no workspace bound");
+  if (!E || !Mx || !My || !Mz || !R) return fail(h, SHASTA_EINVAL, "null field pointer");
+  const EventDesc& d = h->evd[ev];
+  HIPCHECK(h, shasta_launch::write_cons(h->precision == SHASTA_FP32_MIXED, E, Mx, My, Mz, R,
+                                        dev_field(h, ev, h->parity), d.pitch, d.ncell,
+                                        h->stream));
+  if (int rc = refresh_sums(h, ev)) return rc;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->written[ev] = 1;
+  return SHASTA_OK;
+}
+
+int shasta_set_step_index(shasta_t* h, int64_t k) {
+  if (!h) return SHASTA_EINVAL;
+  if (k < 0) return fail(h, SHASTA_EINVAL, "negative step index");
+  h->step_index = k;
+  return SHASTA_OK;
+}
+
+int shasta_get_step_index(const shasta_t* h, int64_t* k) {
+  if (!h || !k) return SHASTA_EINVAL;
+  *k = h->step_index;
+  return SHASTA_OK;
+}
+
+int shasta_step(shasta_t* h, double dt_fm, int nsteps) {
+  if (!h) return SHASTA_EINVAL;
+  if (!(dt_fm > 0.0) || !std::isfinite(dt_fm)) return fail(h, SHASTA_EINVAL, "dt must be > 0");
+  const double lam = dt_fm / h->dx;
+  if (!(lam < 0.5)) return fail(h, SHASTA_EINVAL, "dt/dx must be < 1/2");
+  if (nsteps < 0) return fail(h, SHASTA_EINVAL, "nsteps must be >= 0");
+  if (int rc = check_ready(h)) return rc;
+  int left = nsteps;
+  const bool use_graph = h->graph_enabled && !h->profiling;
+  while (left > 0) {
+    if (use_graph && h->step_index % 6 == 0 && left >= 6) {
+      if (!h->gexec || h->graph_dt != dt_fm || h->graph_parity != h->parity ||
+          h->graph_version != h->tables_version) {
+        if (int rc = capture_cycle(h, dt_fm)) return rc;
+      }
+      while (left >= 6) {
+        HIPCHECK(h, hipGraphLaunch(h->gexec, h->stream));
+        h->step_index += 6;
+        left -= 6;
+        // 18 sweeps: the buffer parity is back where the cycle started
+      }
+      continue;
+    }
+    int parity = h->parity;
+    if (int rc = enqueue_step(h, h->step_index, parity, dt_fm, h->stream)) return rc;
+    h->parity = parity;
+    h->step_index += 1;
+    left -= 1;
+  }
+  return SHASTA_OK;
+}
+
+int shasta_read_field(shasta_t* h, int ev, int field, double* dst) {
+  if (!h) return SHASTA_EINVAL;
+  if (int rc = check_event(h, ev)) return rc;
+  if (field < 0 || field > 10) return fail(h, SHASTA_EINVAL, "field index out of range");
+  if (!dst) return fail(h, SHASTA_EINVAL, "null destination");
+  if (!h->ws || !h->written[ev]) return fail(h, SHASTA_ESTATE, "event not written");
+  const EventDesc& d = h->evd[ev];
+  HIPCHECK(h, shasta_launch::read(h->precision == SHASTA_FP32_MIXED, h->eos,
+                                  dev_field(h, ev, h->parity), d.pitch, d.ncell, field, dst,
+                                  h->stream));
+  double a[A_SIZE];
+  if (int rc = read_acc(h, ev, a)) return rc;
+  if (a[A_NONFINITE] > 0) return fail(h, SHASTA_ENONFINITE, "non-finite values in the fields");
+  return SHASTA_OK;
+}
+
+int shasta_reduce(shasta_t* h, int ev, double out[12], int64_t counters[4]) {
+  if (!h) return SHASTA_EINVAL;
+  if (int rc = check_event(h, ev)) return rc;
+  if (!out || !counters) return fail(h, SHASTA_EINVAL, "null output");
+  if (!h->ws || !h->written[ev]) return fail(h, SHASTA_ESTATE, "event not written");
+  double a[A_SIZE];
+  if (int rc = read_acc(h, ev, a)) return rc;
+  for (int q = 0; q < 5; ++q) {
+    out[q] = a[A_SUM + q];
+    out[5 + q] = a[A_LEDGER + q];
+  }
+  out[10] = a[A_MAXEPS];
+  out[11] = a[A_T];
+  counters[0] = (int64_t)a[A_CLAMP];
+  counters[1] = (int64_t)a[A_FLOOR];
+  counters[2] = (int64_t)a[A_NOCONV];
+  counters[3] = (int64_t)a[A_NONFINITE];
+  if (a[A_NONFINITE] > 0) return fail(h, SHASTA_ENONFINITE, "non-finite values in the fields");
+  return SHASTA_OK;
+}
+
+int shasta_destroy(shasta_t* h) {
+  if (!h) return SHASTA_EINVAL;
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  for (auto& p : h->prof) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  delete h;
+  return SHASTA_OK;
+}
+
+const char* shasta_last_error(const shasta_t* h) { return h ? h->err.c_str() : "null handle"; }
+
+const char* shasta_status_str(int status) {
+  switch (status) {
+    case SHASTA_OK: return "ok";
+    case SHASTA_EINVAL: return "invalid argument";
+    case SHASTA_ESTATE: return "call out of order";
+    case SHASTA_EWORKSPACE: return "workspace missing, too small or misaligned";
+    case SHASTA_EHIP: return "HIP runtime error";
+    case SHASTA_ENONFINITE: return "non-finite value in the fields";
+    case SHASTA_ENOCONVERGE: return "recovery did not converge";
+    default: return "unknown status";
+  }
+}
+
+int shasta_set_tiles(shasta_t* h, int axis, int p0, int p1) {
+  if (!h) return SHASTA_EINVAL;
+  if (axis < 0 || axis > 2) return fail(h, SHASTA_EINVAL, "axis must be 0, 1 or 2");
+  if (p0 < 0) return fail(h, SHASTA_EINVAL, "p0 must be >= 0 (0 = automatic)");
+  if (axis == 0) {
+    h->xwin = p0;
+  } else {
+    if (p1 != 0 && p1 != 16 && p1 != 32 && p1 != 64)
+      return fail(h, SHASTA_EINVAL, "lanes along x must be 16, 32 or 64 (0 = automatic)");
+    if (p0 != 0 && p0 < 16) return fail(h, SHASTA_EINVAL, "segment length must be >= 16");
+    h->seg[axis] = p0;
+    h->lanes[axis] = p1;
+  }
+  build_tables(h);
+  if (h->ws) return upload_tables(h);
+  return SHASTA_OK;
+}
+
+int shasta_get_tiles(const shasta_t* h, int axis, int* p0, int* p1) {
+  if (!h || !p0 || !p1 || axis < 0 || axis > 2) return SHASTA_EINVAL;
+  *p0 = axis == 0 ? h->xwin : h->seg[axis];
+  *p1 = axis == 0 ? 0 : h->lanes[axis];
+  return SHASTA_OK;
+}
+
+int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
+  if (!h) return SHASTA_EINVAL;
+  if (!(dt_fm > 0.0) || !(dt_fm / h->dx < 0.5)) return fail(h, SHASTA_EINVAL, "bad dt");
+  if (reps < 1) reps = 1;
+  if (int rc = check_ready(h)) return rc;
+  const double lam = dt_fm / h->dx;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHECK(h, hipEventCreate(&a));
+  HIPCHECK(h, hipEventCreate(&b));
+  const bool saved_prof = h->profiling;
+  h->profiling = false;
+  int max_n = 0;
+  for (int e = 0; e < h->n_events; ++e)
+    for (int ax = 0; ax < 3; ++ax) max_n = std::max(max_n, h->dims[3 * e + ax]);
+  auto time_axis = [&](int ax, float& ms) -> int {
+    // a sweep reads buffer `parity` and writes the other one, so repeated
+    // sweeps leave the state untouched
+    for (int r = 0; r < 2; ++r)
+      if (int rc = launch_sweep(h, ax, h->parity, 0, lam, h->stream)) return rc;
+    HIPCHECK(h, hipEventRecord(a, h->stream));
+    for (int r = 0; r < reps; ++r)
+      if (int rc = launch_sweep(h, ax, h->parity, 0, lam, h->stream)) return rc;
+    HIPCHECK(h, hipEventRecord(b, h->stream));
+    HIPCHECK(h, hipEventSynchronize(b));
+    HIPCHECK(h, hipEventElapsedTime(&ms, a, b));
+    return SHASTA_OK;
+  };
+  int rc = SHASTA_OK;
+  // x sweep: windows per wave
+  {
+    float best = 1e30f;
+    int best_w = h->xwin;
+    for (int w : {1, 2, 4, 8, 16}) {
+      h->xwin = w;
+      build_tables(h);
+      if ((rc = upload_tables(h))) break;
+      float ms;
+      if ((rc = time_axis(0, ms))) break;
+      if (ms < best) { best = ms; best_w = w; }
+    }
+    h->xwin = best_w;
+  }
+  for (int ax = 1; ax < 3 && rc == SHASTA_OK; ++ax) {
+    float best = 1e30f;
+    int bs = h->seg[ax], bl = h->lanes[ax];
+    for (int lx : {16, 32, 64}) {
+      for (int L : {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1 << 30}) {
+        if (L != (1 << 30) && L >= max_n) continue;
+        h->seg[ax] = (L == (1 << 30)) ? max_n : L;
+        h->lanes[ax] = lx;
+        build_tables(h);
+        if ((rc = upload_tables(h))) break;
+        float ms;
+        if ((rc = time_axis(ax, ms))) break;
+        if (ms < best) { best = ms; bs = h->seg[ax]; bl = lx; }
+      }
+      if (rc) break;
+    }
+    h->seg[ax] = bs;
+    h->lanes[ax] = bl;
+  }
+  build_tables(h);
+  int rc2 = upload_tables(h);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  h->profiling = saved_prof;
+  drop_graph(h);
+  return rc ? rc : rc2;
+}
+
+int shasta_set_graph(shasta_t* h, int enable) {
+  if (!h) return SHASTA_EINVAL;
+  h->graph_enabled = enable != 0;
+  if (!h->graph_enabled) drop_graph(h);
+  return SHASTA_OK;
+}
+
+int shasta_set_profiling(shasta_t* h, int enable) {
+  if (!h) return SHASTA_EINVAL;
+  h->profiling = enable != 0;
+  return SHASTA_OK;
+}
+
+int shasta_read_profile(shasta_t* h, double ms[4], int64_t launches[4]) {
+  if (!h || !ms || !launches) return SHASTA_EINVAL;
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  for (auto& p : h->prof) {
+    float t = 0.f;
+    HIPCHECK(h, hipEventElapsedTime(&t, p.a, p.b));
+    h->prof_ms[p.cls] += t;
+    h->prof_n[p.cls] += 1;
+    h->event_pool.push_back(p.a);
+    h->event_pool.push_back(p.b);
+  }
+  h->prof.clear();
+  for (int c = 0; c < 4; ++c) {
+    ms[c] = h->prof_ms[c];
+    launches[c] = h->prof_n[c];
+    h->prof_ms[c] = 0;
+    h->prof_n[c] = 0;
+  }
+  return SHASTA_OK;
+}
+
+int shasta_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (!src || !dst || bytes % 16) return SHASTA_EINVAL;
+  if (shasta_launch::copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    return SHASTA_EHIP;
+  return SHASTA_OK;
+}
+
+int shasta_selftest_math(const double* in, double* out, int n, int which, void* hip_stream) {
+  if (!in || !out || n < 0 || (which != 0 && which != 1)) return SHASTA_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (n == 0) return SHASTA_OK;
+  if (shasta_launch::selftest(in, out, n, which, st) != hipSuccess) return SHASTA_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return SHASTA_EHIP;
+  return SHASTA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Layouts shared by the host library and the kernels of the relativistic
+// SHASTA step.  Everything here is plain data; no arithmetic of the method.
+#pragma once
+#include <stdint.h>
+
+namespace shasta {
+
+constexpr int kNF = 5;            // E, M_x, M_y, M_z, R
+constexpr int kWavesPerBlock = 4; // 256-thread blocks, each wave independent
+constexpr int kXCells = 4;        // x sweep: consecutive cells owned by a lane
+constexpr int kXMargin = 8;       // x sweep: recomputed cells on each side
+constexpr int kXWindow = 64 * kXCells;             // cells held by one wave
+constexpr int kXOut = kXWindow - 2 * kXMargin;     // cells written per window
+constexpr int kMarchLag = 6;      // y/z sweep: output lags input by 6 cells
+
+// One reduction record per block of every sweep (doubles).
+enum : int {
+  R_SUM = 0,      // 5 sums of the written cells
+  R_LEDGER = 5,   // 5 net boundary outflows of the sweep
+  R_MAXEPS = 10,  // largest |lambda v| of the corrector
+  R_CLAMP = 11,   // recoveries with |M| clamped
+  R_FLOOR = 12,   // recoveries with E floored
+  R_SIZE = 16
+};
+
+// Per-event accumulator (doubles), updated once per step.
+enum : int {
+  A_SUM = 0,
+  A_LEDGER = 5,
+  A_MAXEPS = 10,
+  A_T = 11,
+  A_CLAMP = 12,
+  A_FLOOR = 13,
+  A_NOCONV = 14,
+  A_NONFINITE = 15,
+  A_STEPS = 16,
+  A_INVALID = 17,  // cells rejected by write_primitive
+  A_SIZE = 32
+};
+
+struct EventDesc {
+  int32_t n[3];        // nx, ny, nz
+  int32_t pad0;
+  int64_t ncell;
+  int64_t off[2];      // element offset of field 0 of buffer 0/1; field q
+                       // lives at off[b] + q * pitch
+  int64_t pitch;       // elements between consecutive fields
+  int32_t rec_begin[3];  // first reduction record of this event, per axis
+  int32_t rec_count[3];
+};
+
+// Work of one wave.
+struct Item {
+  int32_t ev;   // event index, -1 = padding (wave does nothing)
+  int32_t a;    // x sweep: first written cell (flat index); y/z: x origin
+  int32_t b;    // x sweep: windows to process; y/z: origin of the other
+                //          transverse axis
+  int32_t s0;   // y/z: written segment [s0, s1) along the sweep axis
+  int32_t s1;
+  int32_t lx;   // y/z: lanes along x (16, 32, 64)
+  int32_t pad[2];
+};
+
+struct EosParams {
+  int32_t kind;  // 0 ideal, 1 bag
+  int32_t pad;
+  double B;
+  double e_H;
+};
+
+}  // namespace shasta

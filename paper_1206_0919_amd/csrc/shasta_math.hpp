@@ -1,0 +1,221 @@
+// Device arithmetic of the relativistic SHASTA step (arXiv:1206.0919).
+//
+// Every function here is shared by the x-sweep and the y/z-sweep kernels, so
+// both organisations of the stencil evaluate identical expressions and their
+// results agree bit for bit.  FP contraction is off for the whole library:
+// every fused multiply-add is written out.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "shasta_internal.hpp"
+
+namespace shasta {
+
+constexpr double kEFloor = 1e-300;       // recovery guard: smallest E
+constexpr double kMFrac = 1.0 - 1e-10;   // recovery guard: largest |M|/E
+constexpr double kThird = 1.0 / 3.0;
+
+// ------------------------------------------------------------ reciprocal, sqrt
+// FP64 reciprocal: hardware estimate refined by two Newton steps
+// (r <- r + r (1 - x r)), accurate to about one ulp for normal x.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  return r;
+}
+// FP32 reciprocal: the hardware estimate is accurate to 1 ulp.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// FP64 square root of a positive normal number: reciprocal square root
+// estimate refined by the coupled Newton (Goldschmidt) iteration for
+// g = sqrt(x), h = 1/(2 sqrt(x)), then two residual corrections.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  const double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  return g;
+}
+
+// -------------------------------------------------------------------- EOS
+// Recovery of the rest frame (Sec. 3, last paragraph).  For an EOS that is
+// linear on a branch, p = a e + b, the condition v (E + p(E - M v)) = M is a
+// quadratic in v whose physical root is v = M w with
+//   w = 2 / (K + sqrt(K^2 - 4 a M^2)),  K = (1 + a) E + b   (a > 0),
+//   w = 1 / (E + b)                                          (a = 0).
+// This is the same root the fixed-point iteration of the paper converges
+// to (the root is unique); it is evaluated directly.  The guard of the
+// recovery (E >= 1e-300, |M| <= (1 - 1e-10) E) is applied here and counted;
+// the conserved fields themselves are never changed.
+//
+// Inputs: E and the momentum along the sweep (Mpar) and across it (Mt1,
+// Mt2).  |M|^2 = Mpar^2 + (Mt1^2 + Mt2^2), symmetric in the transverse pair.
+// Outputs: the velocity along the sweep, the pressure, guard flags.
+struct Recovered {
+  double w;    // v / |M|: velocity component i = w M_i
+  double e;    // rest-frame energy density
+  double p;    // pressure
+  double M2;   // |M|^2 as summed here
+  int clamped;
+  int floored;
+};
+
+// w = v/|M_c| and e for p = e/3, on (E, M^2) of moderate size.
+__device__ __forceinline__ void ideal_root(double E, double M2, double& w,
+                                           double& e) {
+  // v = 3 M / (2 E + sqrt(4 E^2 - 3 M^2)),  e = E - M v
+  const double s = sqrt_pos(__builtin_fma(4.0 * E, E, -3.0 * M2));
+  w = 3.0 * rcp(__builtin_fma(2.0, E, s));
+  e = __builtin_fma(-M2, w, E);
+}
+
+__device__ __forceinline__ void ideal_root_scaled(double E, double M2,
+                                                  double& w, double& e) {
+  // The root is homogeneous of degree 0 in (E, M): solve on (E, M) scaled
+  // by a power of two when the squares would leave the normal range.
+  const int k = __builtin_amdgcn_frexp_exp(E);
+  double ws, es;
+  ideal_root(__builtin_ldexp(E, -k), __builtin_ldexp(M2, -2 * k), ws, es);
+  w = __builtin_ldexp(ws, -k);
+  e = __builtin_ldexp(es, k);
+}
+
+__device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
+                                             double Mpar, double Mt1,
+                                             double Mt2) {
+  Recovered r;
+  const double t = Mt1 * Mt1 + Mt2 * Mt2;
+  const double M2 = __builtin_fma(Mpar, Mpar, t);
+  r.M2 = M2;
+  double Ec = E;
+  r.floored = !(E >= kEFloor);
+  if (r.floored) Ec = kEFloor;
+  const double kE = kMFrac * Ec;
+  const double kE2 = kE * kE;
+  r.clamped = M2 > kE2;
+  const double M2c = r.clamped ? kE2 : M2;
+  double w, e;
+  if (eos.kind == 0) {
+    if (Ec > 1e-140 && Ec < 1e140)
+      ideal_root(Ec, M2c, w, e);
+    else
+      ideal_root_scaled(Ec, M2c, w, e);
+    r.p = e * kThird;
+  } else {
+    // bag model: the recovery function v (E + p(E - M v)) - M increases with
+    // v, so its sign at the edges of the mixed phase selects the branch:
+    // hadron gas if e* <= e_H, plasma if e* >= e_Q, mixed phase otherwise.
+    const double eH = eos.e_H;
+    const double eQ = eos.e_H + 4.0 * eos.B;
+    const double pc = eos.e_H * kThird;
+    const bool hadron = (Ec <= eH) || ((Ec - eH) * (Ec + pc) <= M2c);
+    const bool qgp = !hadron && (Ec > eQ) && ((Ec - eQ) * (Ec + pc) >= M2c);
+    const bool mixed = !hadron && !qgp;
+    if (hadron && !(Ec > 1e-140)) {
+      ideal_root_scaled(Ec, M2c, w, e);
+      r.p = e * kThird;
+    } else {
+      const double b = qgp ? -(4.0 * kThird) * eos.B : 0.0;
+      const double K = __builtin_fma(4.0 * kThird, Ec, b);
+      const double dq =
+          0.5 * (K + sqrt_pos(__builtin_fma(K, K, -(4.0 * kThird) * M2c)));
+      const double den = mixed ? (Ec + pc) : dq;
+      w = rcp(den);
+      e = __builtin_fma(-M2c, w, Ec);
+      r.p = mixed ? pc : __builtin_fma(kThird, e, b);
+    }
+  }
+  // v_i = v M_i / |M| = w M_c M_i / |M|; M_c = |M| unless clamped
+  if (r.clamped) w *= kE * rcp(sqrt_pos(M2));
+  r.w = w;
+  r.e = e;
+  return r;
+}
+
+// ------------------------------------------------------------ SHASTA pieces
+// Geometric factors (eq. shasta-diff) share one reciprocal per interface:
+// Q+_j = (1/2 - eps_j) / D_{j+1/2},  Q-_j = (1/2 + eps_j) / D_{j-1/2},
+// D_{j+1/2} = 1 + (eps_{j+1} - eps_j).
+template <typename T>
+__device__ __forceinline__ T interface_rcp(T eps_left, T eps_right) {
+  return rcp(T(1) + (eps_right - eps_left));
+}
+
+template <typename T>
+struct Coef {
+  T a;  // 1/2 Q+^2
+  T b;  // 1/2 Q-^2
+  T c;  // Q+ + Q-
+};
+
+template <typename T>
+__device__ __forceinline__ Coef<T> coefficients(T eps, T rd_left, T rd_right) {
+  const T qp = (T(0.5) - eps) * rd_right;
+  const T qm = (T(0.5) + eps) * rd_left;
+  Coef<T> k;
+  k.a = T(0.5) * (qp * qp);
+  k.b = T(0.5) * (qm * qm);
+  k.c = qp + qm;
+  return k;
+}
+
+// Source term lambda' Delta(f), Delta(f) = -1/2 (f_{j+1} - f_{j-1});
+// lamsrc = -lambda'/2.
+template <typename T>
+__device__ __forceinline__ T source(T lamsrc, T f_left, T f_right) {
+  return lamsrc * (f_right - f_left);
+}
+
+// Transport with diffusion (eq. shasta-geo):
+// hat U_j = 1/2 Q+^2 Delta_j - 1/2 Q-^2 Delta_{j-1} + (Q+ + Q-) U_j + src.
+template <typename T>
+__device__ __forceinline__ T transport(const Coef<T>& k, T src, T d_right,
+                                       T d_left, T u) {
+  return __builtin_fma(k.a, d_right,
+                       __builtin_fma(-k.b, d_left, __builtin_fma(k.c, u, src)));
+}
+
+// Second difference of Delta used by the phoenical antidiffusion.
+template <typename T>
+__device__ __forceinline__ T second_difference(T d_next, T d_prev, T d) {
+  return (d_next + d_prev) - T(2) * d;
+}
+
+// Phoenical antidiffusion with the strong flux limiter:
+// A^ph_j = diff/8 (hat Delta_j - 1/8 second),  sigma = sgn A^ph_j,
+// A_j = sigma max(0, min(sigma hat Delta_{j+1}, |A^ph_j|, sigma hat Delta_{j-1})).
+// sigma is taken as copysign(1, A^ph); at A^ph = 0 the result is 0 either way.
+template <typename T>
+__device__ __forceinline__ T limited_antiflux(T dh_prev, T dh, T dh_next,
+                                             T second, T diff8) {
+  const T aph = diff8 * __builtin_fma(T(-0.125), second, dh);
+  const T sg = __builtin_copysign(T(1), aph);
+  const T m = __builtin_fmin(__builtin_fmin(sg * dh_next, __builtin_fabs(aph)),
+                             sg * dh_prev);
+  return __builtin_copysign(__builtin_fmax(T(0), m), aph);
+}
+
+// Update (eq. shasta-n): U^{n+1}_j = hat U_j - (A_j - A_{j-1}).
+template <typename T>
+__device__ __forceinline__ T update(T uhat, T a, T a_prev) {
+  return uhat - (a - a_prev);
+}
+
+// Net flux through an outflow face in cell-sum units (only the transport
+// and source parts are non-zero there): eps U + lambda f.
+__device__ __forceinline__ double face_flux(double eps, double u, double lam,
+                                            double f) {
+  return __builtin_fma(eps, u, lam * f);
+}
+
+}  // namespace shasta

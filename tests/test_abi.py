@@ -1,0 +1,95 @@
+"""The C-ABI library loads and exports every symbol include/shasta.h
+declares; host-side argument validation works without touching a GPU (every
+call below returns before its first HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shasta.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(shasta_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_1206_0919_amd import binding
+    return binding
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("shasta_create", "shasta_workspace_bytes", "shasta_bind_workspace",
+              "shasta_set_eos", "shasta_write_primitive", "shasta_write_conserved",
+              "shasta_set_step_index", "shasta_step", "shasta_read_field",
+              "shasta_reduce", "shasta_destroy", "shasta_last_error",
+              "shasta_status_str"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(b):
+    lib = ctypes.CDLL(b.LIB_PATH)
+    for n in declared():
+        assert hasattr(lib, n), n
+    assert set(declared()) == set(b.EXPORTS)
+
+
+def _create(b, n, dims, dx=0.2, prec=0, bc=0):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int32 * len(dims))(*dims)
+    st = b.shasta_create(ctypes.byref(h), n, arr, dx, prec, bc, None)
+    return st, h
+
+
+def test_create_validation(b):
+    assert _create(b, 0, [4, 4, 4])[0] == b.EINVAL
+    assert _create(b, 1, [4, 0, 4])[0] == b.EINVAL
+    assert _create(b, 1, [4, 4, 4], dx=0.0)[0] == b.EINVAL
+    assert _create(b, 1, [4, 4, 4], dx=float("nan"))[0] == b.EINVAL
+    assert _create(b, 1, [4, 4, 4], prec=2)[0] == b.EINVAL
+    assert _create(b, 1, [4, 4, 4], bc=1)[0] == b.EINVAL
+    assert _create(b, 1, [2048, 2048, 1024])[0] == b.EINVAL  # > 2^31 cells
+    st, h = _create(b, 2, [4, 5, 6, 48, 64, 96], prec=1)
+    assert st == b.OK
+    nb = ctypes.c_size_t()
+    assert b.shasta_workspace_bytes(h, ctypes.byref(nb)) == b.OK
+    # two FP32 buffers of 5 fields per event, 64-element pitch
+    assert nb.value >= 4 * 5 * 2 * (128 + 48 * 64 * 96)
+    assert b.shasta_destroy(h) == b.OK
+
+
+def test_state_and_eos_validation(b):
+    st, h = _create(b, 1, [8, 8, 8])
+    assert st == b.OK
+    # step before a workspace is bound
+    assert b.shasta_step(h, 0.08, 1) == b.ESTATE
+    assert b"workspace" in b.shasta_last_error(h)
+    # dt/dx must be in (0, 1/2)
+    assert b.shasta_step(h, 0.1, 1) == b.EINVAL
+    assert b.shasta_step(h, -0.01, 1) == b.EINVAL
+    assert b.shasta_step(h, 0.08, -1) == b.EINVAL
+    p = (ctypes.c_double * 2)(0.4, 0.1)
+    assert b.shasta_set_eos(h, 1, p, 2) == b.OK
+    assert b.shasta_set_eos(h, 1, p, 1) == b.EINVAL
+    bad = (ctypes.c_double * 2)(-1.0, 0.1)
+    assert b.shasta_set_eos(h, 1, bad, 2) == b.EINVAL
+    assert b.shasta_set_eos(h, 7, None, 0) == b.EINVAL
+    assert b.shasta_set_eos(h, 0, None, 0) == b.OK
+    assert b.shasta_set_step_index(h, -3) == b.EINVAL
+    assert b.shasta_set_tiles(h, 1, 8, 16) == b.EINVAL   # segment < 16
+    assert b.shasta_set_tiles(h, 2, 32, 48) == b.EINVAL  # lanes not 16/32/64
+    assert b.shasta_set_tiles(h, 3, 32, 16) == b.EINVAL
+    assert b.shasta_set_tiles(h, 1, 32, 16) == b.OK
+    out = (ctypes.c_double * 12)()
+    cnt = (ctypes.c_int64 * 4)()
+    assert b.shasta_reduce(h, 1, out, cnt) == b.EINVAL
+    assert b.shasta_reduce(h, 0, out, cnt) == b.ESTATE
+    assert b.shasta_read_field(h, 0, 11, None) == b.EINVAL
+    assert b.shasta_destroy(h) == b.OK
+    assert b.shasta_status_str(b.ENONFINITE) == b"non-finite value in the fields"
