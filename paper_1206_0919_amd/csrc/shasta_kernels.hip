@@ -138,7 +138,7 @@ __device__ __forceinline__ void pipe_shift(FieldPipe<T>& f, T un, T d_new,
 }
 
 // AXIS = 1 (y) or 2 (z).
-template <typename T, int AXIS>
+template <typename T, int AXIS, int EOS>
 __global__ __launch_bounds__(256) void sweep_march(SweepArgs A) {
   constexpr int QP = 1 + AXIS;                   // momentum along the sweep
   constexpr int QT1 = 1;                         // the transverse momenta
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void sweep_march(SweepArgs A) {
         for (int q = 0; q < kNF; ++q) qb[q] = src[q * pitch + o2];
       }
       // ---- recovery at U^n of cell i
-      const Recovered rn = recover(A.eos, double(un[0]), double(un[QP]),
+      const Recovered rn = recover<EOS>(A.eos, double(un[0]), double(un[QP]),
                                    double(un[QT1]), double(un[QT2]));
       const double vn = rn.w * double(un[QP]);
       const T ep_i = T(lamh * vn);
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void sweep_march(SweepArgs A) {
       } else if (k >= N) {
         ec_k = ec2; fEc_k = fEc2; fMc_k = fMc2;        // copy of cell N-1
       } else {
-        const Recovered rh = recover(A.eos, double(uh[0]), double(uh[QP]),
+        const Recovered rh = recover<EOS>(A.eos, double(uh[0]), double(uh[QP]),
                                      double(uh[QT1]), double(uh[QT2]));
         const double vh = rh.w * double(uh[QP]);
         ec_k = T(lam * vh);
@@ -431,7 +431,7 @@ __device__ __forceinline__ void x_coefficients(const T (&eps)[kXCells],
   }
 }
 
-template <typename T>
+template <typename T, int EOS>
 __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
   constexpr int QP = 1, QT1 = 2, QT2 = 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
       T ep[kXCells], fE[kXCells], fM[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered rn = recover(A.eos, double(u[0][j]), double(u[QP][j]),
+        const Recovered rn = recover<EOS>(A.eos, double(u[0][j]), double(u[QP][j]),
                                      double(u[QT1][j]), double(u[QT2][j]));
         const double v = rn.w * double(u[QP][j]);
         ep[j] = T(lamh * v);
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
       T ec[kXCells], fEc[kXCells], fMc[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered rh = recover(A.eos, double(uh[0][j]), double(uh[QP][j]),
+        const Recovered rh = recover<EOS>(A.eos, double(uh[0][j]), double(uh[QP][j]),
                                      double(uh[QT1][j]), double(uh[QT2][j]));
         const double v = rh.w * double(uh[QP][j]);
         ec[j] = T(lam * v);
@@ -691,7 +691,8 @@ __global__ void read_out(EosParams eos, const T* in, int64_t pitch, int64_t ncel
     }
     const double E = in[i], Mx = in[pitch + i], My = in[2 * pitch + i],
                  Mz = in[3 * pitch + i], R = in[4 * pitch + i];
-    const Recovered r = recover(eos, E, Mx, My, Mz);
+    const Recovered r = (eos.kind == 0) ? recover<0>(eos, E, Mx, My, Mz)
+                                        : recover<1>(eos, E, Mx, My, Mz);
     double out;
     switch (field) {
       case 5: out = r.e; break;
@@ -758,15 +759,15 @@ __global__ void selftest_kernel(const double* in, double* out, int n, int which)
 }
 
 // ------------------------------------------------------------ launchers
-template <typename T>
+template <typename T, int EOS>
 hipError_t launch_sweep(int axis, const SweepArgs& a, hipStream_t st) {
   const dim3 grid(a.n_items / kWavesPerBlock), block(64 * kWavesPerBlock);
   if (axis == 0)
-    hipLaunchKernelGGL(sweep_x<T>, grid, block, 0, st, a);
+    hipLaunchKernelGGL((sweep_x<T, EOS>), grid, block, 0, st, a);
   else if (axis == 1)
-    hipLaunchKernelGGL((sweep_march<T, 1>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((sweep_march<T, 1, EOS>), grid, block, 0, st, a);
   else
-    hipLaunchKernelGGL((sweep_march<T, 2>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((sweep_march<T, 2, EOS>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 
@@ -778,7 +779,9 @@ using namespace shasta;
 
 hipError_t sweep(int fp32, int axis, const void* args, hipStream_t st) {
   const SweepArgs& a = *static_cast<const SweepArgs*>(args);
-  return fp32 ? launch_sweep<float>(axis, a, st) : launch_sweep<double>(axis, a, st);
+  if (a.eos.kind == 0)
+    return fp32 ? launch_sweep<float, 0>(axis, a, st) : launch_sweep<double, 0>(axis, a, st);
+  return fp32 ? launch_sweep<float, 1>(axis, a, st) : launch_sweep<double, 1>(axis, a, st);
 }
 
 hipError_t finalize(const EventDesc* ev, int n_events, const double* const rec[3],

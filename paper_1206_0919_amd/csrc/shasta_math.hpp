@@ -90,6 +90,15 @@ __device__ __forceinline__ void ideal_root_scaled(double E, double M2,
   e = __builtin_ldexp(es, k);
 }
 
+// True if any lane of the wave has pred set (a wave-uniform branch lets the
+// rare paths below cost nothing when no lane takes them).
+__device__ __forceinline__ bool any_lane(bool pred) {
+  return __builtin_amdgcn_ballot_w64(pred) != 0;
+}
+
+// EOS: 0 = ideal gas p = e/3, 1 = bag model (compile-time, as the paper
+// specialises its kernels per EOS instead of branching at run time).
+template <int EOS>
 __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
                                              double Mpar, double Mt1,
                                              double Mt2) {
@@ -97,19 +106,19 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
   const double t = Mt1 * Mt1 + Mt2 * Mt2;
   const double M2 = __builtin_fma(Mpar, Mpar, t);
   r.M2 = M2;
-  double Ec = E;
   r.floored = !(E >= kEFloor);
-  if (r.floored) Ec = kEFloor;
+  const double Ec = r.floored ? kEFloor : E;
   const double kE = kMFrac * Ec;
   const double kE2 = kE * kE;
   r.clamped = M2 > kE2;
   const double M2c = r.clamped ? kE2 : M2;
   double w, e;
-  if (eos.kind == 0) {
-    if (Ec > 1e-140 && Ec < 1e140)
-      ideal_root(Ec, M2c, w, e);
-    else
-      ideal_root_scaled(Ec, M2c, w, e);
+  if constexpr (EOS == 0) {
+    const bool rare = !(Ec > 1e-140 && Ec < 1e140);
+    ideal_root(Ec, M2c, w, e);
+    if (any_lane(rare)) {
+      if (rare) ideal_root_scaled(Ec, M2c, w, e);
+    }
     r.p = e * kThird;
   } else {
     // bag model: the recovery function v (E + p(E - M v)) - M increases with
@@ -121,22 +130,26 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
     const bool hadron = (Ec <= eH) || ((Ec - eH) * (Ec + pc) <= M2c);
     const bool qgp = !hadron && (Ec > eQ) && ((Ec - eQ) * (Ec + pc) >= M2c);
     const bool mixed = !hadron && !qgp;
-    if (hadron && !(Ec > 1e-140)) {
-      ideal_root_scaled(Ec, M2c, w, e);
-      r.p = e * kThird;
-    } else {
-      const double b = qgp ? -(4.0 * kThird) * eos.B : 0.0;
-      const double K = __builtin_fma(4.0 * kThird, Ec, b);
-      const double dq =
-          0.5 * (K + sqrt_pos(__builtin_fma(K, K, -(4.0 * kThird) * M2c)));
-      const double den = mixed ? (Ec + pc) : dq;
-      w = rcp(den);
-      e = __builtin_fma(-M2c, w, Ec);
-      r.p = mixed ? pc : __builtin_fma(kThird, e, b);
+    const double b = qgp ? -(4.0 * kThird) * eos.B : 0.0;
+    const double K = __builtin_fma(4.0 * kThird, Ec, b);
+    const double dq =
+        0.5 * (K + sqrt_pos(__builtin_fma(K, K, -(4.0 * kThird) * M2c)));
+    const double den = mixed ? (Ec + pc) : dq;
+    w = rcp(den);
+    e = __builtin_fma(-M2c, w, Ec);
+    r.p = mixed ? pc : __builtin_fma(kThird, e, b);
+    const bool rare = hadron && !(Ec > 1e-140);
+    if (any_lane(rare)) {
+      if (rare) {
+        ideal_root_scaled(Ec, M2c, w, e);
+        r.p = e * kThird;
+      }
     }
   }
   // v_i = v M_i / |M| = w M_c M_i / |M|; M_c = |M| unless clamped
-  if (r.clamped) w *= kE * rcp(sqrt_pos(M2));
+  if (any_lane(r.clamped)) {
+    if (r.clamped) w *= kE * rcp(sqrt_pos(M2));
+  }
   r.w = w;
   r.e = e;
   return r;

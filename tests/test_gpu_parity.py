@@ -34,9 +34,9 @@ def B(torch):
     return binding
 
 
-def gpu_state(B, torch, prim, precision=0, eos=None, dims=None):
+def gpu_state(B, torch, prim, precision=0, eos=None, dx=DX):
     nz, ny, nx = prim.e.shape
-    s = B.Shasta([(nx, ny, nz)], DX, precision=precision, eos=eos)
+    s = B.Shasta([(nx, ny, nz)], dx, precision=precision, eos=eos)
     s.write_primitive(0, *[torch.from_numpy(a) for a in prim.as_tuple()])
     return s
 
@@ -163,15 +163,16 @@ def test_step_axis_permutation_equivariance_bitwise(B, torch, orc, swap, k_a, k_
     prim = inputs.Primitive(pr.e, v[0], v[1], v[2], pr.n)
     perm = [0, 1, 2]
     perm[2 - a], perm[2 - b] = perm[2 - b], perm[2 - a]
-    vel = [prim.vx, prim.vy, prim.vz]
-    tv = [np.ascontiguousarray(x.transpose(perm)) for x in vel]
-    tv[a], tv[b] = tv[b], tv[a]
-    tprim = inputs.Primitive(np.ascontiguousarray(prim.e.transpose(perm)), tv[0], tv[1],
-                             tv[2], np.ascontiguousarray(prim.n.transpose(perm)))
     s1 = gpu_state(B, torch, prim)
+    U0 = read_np(s1)
+    # the transposed conserved state, momentum components relabelled
+    T0 = [np.ascontiguousarray(x.transpose(perm)) for x in U0]
+    T0[1 + a], T0[1 + b] = T0[1 + b], T0[1 + a]
+    nz, ny, nx = T0[0].shape
+    s2 = B.Shasta([(nx, ny, nz)], DX)
+    s2.write_conserved(0, *[torch.from_numpy(x) for x in T0])
     s1.set_step_index(k_a)
     s1.step(DT, 1)
-    s2 = gpu_state(B, torch, tprim)
     s2.set_step_index(k_b)
     s2.step(DT, 1)
     U1, U2 = read_np(s1), read_np(s2)
@@ -269,8 +270,8 @@ def test_bag_eos_fp64_vs_oracle(B, torch, orc_bag):
     Bc, e_H = inputs.bag_parameters()
     dims = (30, 28, 26)
     prim = inputs.hotspots(dims, 0.1, 10, seed=6, amp=(0.5, 6.0), e_bg=0.01,
-                           vz_profile=inputs.longitudinal_flow)
-    s = gpu_state(B, torch, prim, eos=(B.EOS_BAG, (Bc, e_H)))
+                           sigma=0.3, vz_profile=inputs.longitudinal_flow)
+    s = gpu_state(B, torch, prim, eos=(B.EOS_BAG, (Bc, e_H)), dx=0.1)
     s.step(0.04, 12)
     got = read_np(s)
     U = to_cons(orc_bag, prim)
