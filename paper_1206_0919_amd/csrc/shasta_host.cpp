@@ -49,6 +49,7 @@ struct SweepArgsHost {
   double lam;
   double diff;
   double* rec;
+  const int2* xwin;
   EosParams eos;
 };
 
@@ -81,6 +82,7 @@ struct shasta_handle {
 
   // tables
   std::vector<EventDesc> evd;
+  std::vector<int2> xwins;          // x-sweep windows of all events
   std::vector<Item> items[3];
   int n_records[3] = {0, 0, 0};
   int64_t item_cap[3] = {0, 0, 0};
@@ -89,7 +91,7 @@ struct shasta_handle {
   // workspace layout
   size_t elem = 8;
   size_t field_bytes = 0, off_ev = 0, off_items[3] = {0, 0, 0}, off_rec = 0,
-         off_acc = 0, off_scratch = 0, total = 0;
+         off_acc = 0, off_scratch = 0, off_xwin = 0, total = 0;
   char* ws = nullptr;
   size_t ws_len = 0;
 
@@ -166,6 +168,29 @@ int64_t columns(const shasta_t* h, int axis, int ev, int lx) {
   return (int64_t)((nx + lx - 1) / lx) * ((nb + lb - 1) / lb);
 }
 
+// x-sweep windows of one event: consecutive cell ranges [c0, c1) whose row
+// pieces, each with a halo of kHalo positions on both sides, fill at most
+// kXWindow positions.
+void build_xwindows(int nx, int64_t ncell, std::vector<int2>& out) {
+  int64_t c = 0;
+  while (c < ncell) {
+    const int64_t c0 = c;
+    int pos = 0;
+    while (c < ncell) {
+      const int64_t len = std::min<int64_t>(nx - c % nx, ncell - c);
+      if (pos + len + 2 * kHalo <= kXWindow) {
+        pos += (int)len + 2 * kHalo;
+        c += len;
+      } else {
+        const int take = kXWindow - pos - 2 * kHalo;
+        if (take >= 1) c += take;
+        break;
+      }
+    }
+    out.push_back(make_int2((int)c0, (int)c));
+  }
+}
+
 // Build the per-axis work lists.  Every event's list is padded to a whole
 // number of blocks so a block never mixes events.
 void build_tables(shasta_t* h) {
@@ -176,22 +201,20 @@ void build_tables(shasta_t* h) {
     for (int e = 0; e < ne; ++e) waves_full[ax] += columns(h, ax, e, lanes_for(h, ax, e));
   const int64_t target_waves = 2048;  // 2 waves on each of 1024 SIMDs
   for (int ax = 0; ax < 3; ++ax) h->items[ax].clear();
-  int64_t total_windows = 0;
-  for (int e = 0; e < ne; ++e) total_windows += (ncell_of(h, e) + kXOut - 1) / kXOut;
-  int auto_xwin = (int)std::max<int64_t>(1, total_windows / 4096);
+  const int64_t total_windows = (int64_t)h->xwins.size();
+  const int auto_xwin = (int)std::max<int64_t>(1, total_windows / 8192);
   for (int ax = 0; ax < 3; ++ax) {
     int rec = 0;
     for (int e = 0; e < ne; ++e) {
       EventDesc& d = h->evd[e];
       const size_t start = h->items[ax].size();
       if (ax == 0) {
-        const int64_t nc = ncell_of(h, e);
-        const int64_t nwin = (nc + kXOut - 1) / kXOut;
+        const int64_t nwin = d.xwin_count;
         const int per = h->xwin ? h->xwin : auto_xwin;
         for (int64_t w = 0; w < nwin; w += per) {
           Item it{};
           it.ev = e;
-          it.a = (int32_t)(w * kXOut);
+          it.a = (int32_t)w;
           it.b = (int32_t)std::min<int64_t>(per, nwin - w);
           h->items[ax].push_back(it);
         }
@@ -246,7 +269,7 @@ void table_capacity(const shasta_t* h, int64_t cap[3], int64_t& rec_cap) {
     for (int e = 0; e < h->n_events; ++e) {
       int64_t m;
       if (ax == 0) {
-        m = (ncell_of(h, e) + kXOut - 1) / kXOut;
+        m = h->evd[e].xwin_count;
       } else {
         const int N = h->dims[3 * e + ax];
         int64_t worst = 0;
@@ -277,6 +300,13 @@ void layout(shasta_t* h) {
     off += kNF * d.pitch;
   }
   h->field_bytes = align256((size_t)off * h->elem);
+  h->xwins.clear();
+  for (int e = 0; e < h->n_events; ++e) {
+    EventDesc& d = h->evd[e];
+    d.xwin_begin = (int32_t)h->xwins.size();
+    build_xwindows(d.n[0], d.ncell, h->xwins);
+    d.xwin_count = (int32_t)(h->xwins.size() - d.xwin_begin);
+  }
   table_capacity(h, h->item_cap, h->rec_cap);
   size_t p = h->field_bytes;
   h->off_ev = p;
@@ -291,6 +321,8 @@ void layout(shasta_t* h) {
   p = align256(p + sizeof(double) * A_SIZE * h->n_events);
   h->off_scratch = p;
   p = align256(p + sizeof(double) * shasta_launch::sum_scratch_doubles());
+  h->off_xwin = p;
+  p = align256(p + sizeof(int2) * h->xwins.size());
   h->total = p;
 }
 
@@ -312,6 +344,8 @@ int upload_tables(shasta_t* h) {
       return fail(h, SHASTA_EWORKSPACE, "work table exceeds the workspace capacity");
   HIPCHECK(h, hipMemcpyAsync(dev_events(h), h->evd.data(), sizeof(EventDesc) * h->n_events,
                              hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipMemcpyAsync(h->ws + h->off_xwin, h->xwins.data(),
+                             sizeof(int2) * h->xwins.size(), hipMemcpyHostToDevice, h->stream));
   for (int ax = 0; ax < 3; ++ax)
     HIPCHECK(h, hipMemcpyAsync(dev_items(h, ax), h->items[ax].data(),
                                sizeof(Item) * h->items[ax].size(), hipMemcpyHostToDevice,
@@ -349,6 +383,7 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
   a.lam = lam;
   a.diff = h->diff;
   a.rec = dev_rec(h, slot);
+  a.xwin = reinterpret_cast<const int2*>(h->ws + h->off_xwin);
   a.eos = h->eos;
   if (a.n_items == 0) return SHASTA_OK;
   const bool prof = h->profiling && st == h->stream;
@@ -733,7 +768,7 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
   {
     float best = 1e30f;
     int best_w = h->xwin;
-    for (int w : {1, 2, 4, 8, 16}) {
+    for (int w : {1, 2, 3, 4, 6, 8, 12, 16}) {
       h->xwin = w;
       build_tables(h);
       if ((rc = upload_tables(h))) break;

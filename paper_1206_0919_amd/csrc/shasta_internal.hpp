@@ -7,10 +7,9 @@ namespace shasta {
 
 constexpr int kNF = 5;            // E, M_x, M_y, M_z, R
 constexpr int kWavesPerBlock = 4; // 256-thread blocks, each wave independent
-constexpr int kXCells = 4;        // x sweep: consecutive cells owned by a lane
-constexpr int kXMargin = 8;       // x sweep: recomputed cells on each side
-constexpr int kXWindow = 64 * kXCells;             // cells held by one wave
-constexpr int kXOut = kXWindow - 2 * kXMargin;     // cells written per window
+constexpr int kXCells = 4;        // x sweep: consecutive positions per lane
+constexpr int kXWindow = 64 * kXCells;  // positions held by one wave
+constexpr int kHalo = 6;          // halo of a row piece (two half steps of 3)
 constexpr int kMarchLag = 6;      // y/z sweep: output lags input by 6 cells
 
 // One reduction record per block of every sweep (doubles).
@@ -47,12 +46,15 @@ struct EventDesc {
   int64_t pitch;       // elements between consecutive fields
   int32_t rec_begin[3];  // first reduction record of this event, per axis
   int32_t rec_count[3];
+  int32_t xwin_begin;    // first x-sweep window of this event
+  int32_t xwin_count;
 };
 
 // Work of one wave.
 struct Item {
   int32_t ev;   // event index, -1 = padding (wave does nothing)
-  int32_t a;    // x sweep: first written cell (flat index); y/z: x origin
+  int32_t a;    // x sweep: first window (index in the event's windows);
+                //          y/z: x origin
   int32_t b;    // x sweep: windows to process; y/z: origin of the other
                 //          transverse axis
   int32_t s0;   // y/z: written segment [s0, s1) along the sweep axis

@@ -36,6 +36,7 @@ struct SweepArgs {
   double lam;          // dt / dx
   double diff;         // antidiffusion scale (1: phoenical)
   double* rec;         // reduction records of this sweep, one per block
+  const int2* xwin;    // x sweep: cell range [c0, c1) of every window
   EosParams eos;
 };
 
@@ -71,371 +72,324 @@ __device__ __forceinline__ void block_record(double (&acc)[13], double* rec) {
 }
 
 // ------------------------------------------------------------ march (y, z)
-// Per-field pipeline state.  Index convention at iteration i (cell i of U^n
-// just loaded): names give the cell they refer to.
+// Buffer descriptor of one field array (raw addressing, range checked by the
+// hardware: loads beyond num_records return 0, stores beyond are dropped).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
 template <typename T>
-struct FieldPipe {
-  T u1, u2, u3, u4;  // U^n at i-4, i-3, i-2, i-1
-  T d1, d2, d3, d4;  // Delta = U_{j+1} - U_j at j = i-5, i-4, i-3, i-2
-  T q1, q2, q3;      // second difference of Delta at i-6, i-5, i-4
-  T hp1, hp2;        // predictor hat U at i-3, i-2
-  T gp1, gp2;        // predictor hat Delta at i-4, i-3
-  T ap1;             // predictor antiflux at i-4
-  T hc1, hc2;        // corrector hat U at i-6, i-5
-  T gc1, gc2;        // corrector hat Delta at i-7, i-6
-  T ac1;             // corrector antiflux at i-7
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(
+        __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), v), r, off, 0, 0);
+}
+
+// The march keeps every windowed quantity in a ring of 8 slots: the value of
+// cell p lives in slot (p - i_lo) & 7.  The loop body is instantiated for the
+// 8 phases, so every slot index is a compile-time constant and the windows
+// never move between registers.  At iteration i (cell i of U^n consumed):
+//   predictor: hat U of cell i-1, hat Delta of i-2, antiflux and U^{n+1/2}
+//              of cell i-3;
+//   recovery of U^{n+1/2} at cell i-3;
+//   corrector: hat U of cell i-4, hat Delta of i-5, antiflux and U^{n+1} of
+//              cell i-6.
+// Longest slot lifetime: U^n of a cell is loaded 2 iterations ahead and last
+// used 4 iterations after (7 < 8 slots).
+template <typename T, int AXIS, int EOS>
+struct March {
+  static constexpr int QP = 1 + AXIS;            // momentum along the sweep
+  static constexpr int QT1 = 1;                  // transverse momenta
+  static constexpr int QT2 = (AXIS == 1) ? 3 : 2;
+
+  T u[kNF][8], d[kNF][8], q2[kNF][8];
+  T hp[kNF][8], gp[kNF][8], ap[kNF][8];
+  T hc[kNF][8], gc[kNF][8], ac[kNF][8];
+  T ep[8], fEp[8], fMp[8], rdp[8];
+  T ec[8], fEc[8], fMc[8], rdc[8];
+
+  __amdgpu_buffer_rsrc_t src[kNF], dst[kNF];
+  int off_col;      // byte offset of the lane's column
+  int step_bytes;   // bytes between consecutive cells along the sweep
+  int N, s0, s1, i_lo;
+  bool active;
+  const EosParams* eos;
+  double lam, lamh;
+  T lamsrc_p, lamsrc_c, diff8;
+  double acc[13];
+
+  __device__ __forceinline__ int off_of(int i) const {
+    return off_col + min(max(i, 0), N - 1) * step_bytes;
+  }
+
+  template <int PH>
+  __device__ __forceinline__ void load(int i) {
+    const int o = off_of(i);
+#pragma unroll
+    for (int q = 0; q < kNF; ++q) u[q][PH & 7] = buf_load<T>(src[q], o);
+  }
+
+  template <int PH>
+  __device__ __forceinline__ void iterate(int i) {
+    constexpr int S0 = PH & 7, S1 = (PH - 1) & 7, S2 = (PH - 2) & 7, S3 = (PH - 3) & 7,
+                  S4 = (PH - 4) & 7, S5 = (PH - 5) & 7, S6 = (PH - 6) & 7, S7 = (PH - 7) & 7;
+    load<PH + 2>(i + 2);  // prefetch
+    // ---- recovery at U^n of cell i
+    {
+      const Recovered r = recover<EOS>(*eos, double(u[0][S0]), double(u[QP][S0]),
+                                       double(u[QT1][S0]), double(u[QT2][S0]));
+      const double v = r.w * double(u[QP][S0]);
+      ep[S0] = T(lamh * v);
+      fEp[S0] = T(r.p * v);
+      fMp[S0] = T(r.p);
+      if (active && i >= s0 && i < s1) {
+        acc[R_CLAMP] += r.clamped;
+        acc[R_FLOOR] += r.floored;
+      }
+    }
+    // ---- predictor of cell i-1 .. U^{n+1/2} of cell i-3
+    rdp[S0] = interface_rcp(ep[S1], ep[S0]);
+    const Coef<T> kp = coefficients(ep[S1], rdp[S1], rdp[S0]);
+    const T sEp = source(lamsrc_p, fEp[S2], fEp[S0]);
+    const T sMp = source(lamsrc_p, fMp[S2], fMp[S0]);
+    T uh[kNF];
+#pragma unroll
+    for (int q = 0; q < kNF; ++q) {
+      const T s = (q == 0) ? sEp : ((q == QP) ? sMp : T(0));
+      d[q][S1] = u[q][S0] - u[q][S1];                                    // Delta_{i-1}
+      hp[q][S1] = transport(kp, s, d[q][S1], d[q][S2], u[q][S1]);        // hat U_{i-1}
+      gp[q][S2] = hp[q][S1] - hp[q][S2];                                 // hat Delta_{i-2}
+      q2[q][S3] = second_difference(d[q][S2], d[q][S4], d[q][S3]);      // at i-3
+      ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], q2[q][S3], diff8);
+      uh[q] = update(hp[q][S3], ap[q][S3], ap[q][S4]);                  // U^{n+1/2}_{i-3}
+    }
+    // ---- recovery at U^{n+1/2} of cell k = i-3 (halo cells copy the edge)
+    const int k = i - 3;
+    if (k < 0) {
+      ec[S3] = T(0); fEc[S3] = T(0); fMc[S3] = T(0);      // replaced at k = 0
+    } else if (k >= N) {
+      ec[S3] = ec[S4]; fEc[S3] = fEc[S4]; fMc[S3] = fMc[S4];
+    } else {
+      const Recovered r = recover<EOS>(*eos, double(uh[0]), double(uh[QP]),
+                                       double(uh[QT1]), double(uh[QT2]));
+      const double v = r.w * double(uh[QP]);
+      ec[S3] = T(lam * v);
+      fEc[S3] = T(r.p * v);
+      fMc[S3] = T(r.p);
+      if (active && k >= s0 && k < s1) {
+        acc[R_CLAMP] += r.clamped;
+        acc[R_FLOOR] += r.floored;
+        acc[R_MAXEPS] = fmax(acc[R_MAXEPS], fabs(double(ec[S3])));
+      }
+    }
+    const bool left_edge = (k == 0);
+    if (left_edge) {
+      ec[S4] = ec[S5] = ec[S3];
+      fEc[S4] = fEc[S5] = fEc[S3];
+      fMc[S4] = fMc[S5] = fMc[S3];
+      rdc[S4] = interface_rcp(ec[S5], ec[S4]);
+    }
+    // ---- boundary ledger: flux through the outflow faces (corrector)
+    if (active && ((left_edge && s0 == 0) || (k == N - 1 && s1 == N))) {
+      const double e64 = double(ec[S3]);
+#pragma unroll
+      for (int q = 0; q < kNF; ++q) {
+        const double f = (q == 0) ? double(fEc[S3]) : ((q == QP) ? double(fMc[S3]) : 0.0);
+        const double F = face_flux(e64, double(u[q][S3]), lam, f);
+        if (left_edge) acc[R_LEDGER + q] -= F;
+        if (k == N - 1) acc[R_LEDGER + q] += F;
+      }
+    }
+    // ---- corrector of cell i-4 .. U^{n+1} of cell o = i-6
+    rdc[S3] = interface_rcp(ec[S4], ec[S3]);
+    const Coef<T> kc = coefficients(ec[S4], rdc[S4], rdc[S3]);
+    const T sEc = source(lamsrc_c, fEc[S5], fEc[S3]);
+    const T sMc = source(lamsrc_c, fMc[S5], fMc[S3]);
+    const int o = i - kMarchLag;
+    const bool store = active && o >= s0 && o < s1;
+    const int ooff = off_col + o * step_bytes;
+#pragma unroll
+    for (int q = 0; q < kNF; ++q) {
+      const T s = (q == 0) ? sEc : ((q == QP) ? sMc : T(0));
+      hc[q][S4] = transport(kc, s, d[q][S4], d[q][S5], u[q][S4]);       // hat U_{i-4}
+      if (left_edge) hc[q][S5] = hc[q][S4];                              // halo: hat U_{-2}
+      gc[q][S5] = hc[q][S4] - hc[q][S5];                                 // hat Delta_{i-5}
+      ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], diff8);
+      const T out = update(hc[q][S6], ac[q][S6], ac[q][S7]);            // U^{n+1}_{i-6}
+      if (store) {
+        buf_store<T>(dst[q], ooff, out);
+        acc[R_SUM + q] += double(out);
+      }
+    }
+  }
 };
-
-template <typename T>
-__device__ __forceinline__ void pipe_zero(FieldPipe<T>& f) {
-  f.u1 = f.u2 = f.u3 = f.u4 = T(0);
-  f.d1 = f.d2 = f.d3 = f.d4 = T(0);
-  f.q1 = f.q2 = f.q3 = T(0);
-  f.hp1 = f.hp2 = f.gp1 = f.gp2 = f.ap1 = T(0);
-  f.hc1 = f.hc2 = f.gc1 = f.gc2 = f.ac1 = T(0);
-}
-
-// Predictor stage of one field; returns U^{n+1/2} at cell i-3.
-template <typename T>
-__device__ __forceinline__ T pipe_predict(FieldPipe<T>& f, T un,
-                                          const Coef<T>& k, T src, T diff8,
-                                          T& d_new, T& hp_new, T& gp_new,
-                                          T& q_new, T& ap_new) {
-  d_new = un - f.u4;                                    // Delta_{i-1}
-  hp_new = transport(k, src, d_new, f.d4, f.u4);        // hat U_{i-1}
-  gp_new = hp_new - f.hp2;                              // hat Delta_{i-2}
-  q_new = second_difference(f.d4, f.d2, f.d3);          // at i-3
-  ap_new = limited_antiflux(f.gp1, f.gp2, gp_new, q_new, diff8);  // A_{i-3}
-  return update(f.hp1, ap_new, f.ap1);                  // U^{n+1/2}_{i-3}
-}
-
-// Corrector stage of one field; returns U^{n+1} at cell i-6.
-template <typename T>
-__device__ __forceinline__ T pipe_correct(FieldPipe<T>& f, const Coef<T>& k,
-                                          T src, T diff8, bool left_edge,
-                                          T& hc_new, T& gc_new, T& ac_new) {
-  hc_new = transport(k, src, f.d2, f.d1, f.u1);         // hat U_{i-4}
-  if (left_edge) f.hc2 = hc_new;                        // halo: hat U_{-2} = hat U_{-1}
-  gc_new = hc_new - f.hc2;                              // hat Delta_{i-5}
-  ac_new = limited_antiflux(f.gc1, f.gc2, gc_new, f.q1, diff8);   // A_{i-6}
-  return update(f.hc1, ac_new, f.ac1);                  // U^{n+1}_{i-6}
-}
-
-template <typename T>
-__device__ __forceinline__ void pipe_shift(FieldPipe<T>& f, T un, T d_new,
-                                           T hp_new, T gp_new, T q_new,
-                                           T ap_new, T hc_new, T gc_new,
-                                           T ac_new) {
-  f.u1 = f.u2; f.u2 = f.u3; f.u3 = f.u4; f.u4 = un;
-  f.d1 = f.d2; f.d2 = f.d3; f.d3 = f.d4; f.d4 = d_new;
-  f.q1 = f.q2; f.q2 = f.q3; f.q3 = q_new;
-  f.hp1 = f.hp2; f.hp2 = hp_new;
-  f.gp1 = f.gp2; f.gp2 = gp_new;
-  f.ap1 = ap_new;
-  f.hc1 = f.hc2; f.hc2 = hc_new;
-  f.gc1 = f.gc2; f.gc2 = gc_new;
-  f.ac1 = ac_new;
-}
 
 // AXIS = 1 (y) or 2 (z).
 template <typename T, int AXIS, int EOS>
 __global__ __launch_bounds__(256) void sweep_march(SweepArgs A) {
-  constexpr int QP = 1 + AXIS;                   // momentum along the sweep
-  constexpr int QT1 = 1;                         // the transverse momenta
-  constexpr int QT2 = (AXIS == 1) ? 3 : 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int item_id = blockIdx.x * kWavesPerBlock + wave;
-  double acc[13];
+  // wave-uniform: lets the compiler keep the work item in scalar registers
+  const int item_id = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave);
+  March<T, AXIS, EOS> M;
 #pragma unroll
-  for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+  for (int j = 0; j < 13; ++j) M.acc[j] = 0.0;
 
   const Item it = A.items[item_id];
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
     const int nx = ev.n[0], ny = ev.n[1];
-    const int N = ev.n[AXIS];
+    M.N = ev.n[AXIS];
     const int nb = (AXIS == 1) ? ev.n[2] : ev.n[1];
-    const int64_t s_ax = (AXIS == 1) ? (int64_t)nx : (int64_t)nx * ny;
-    const int64_t s_b = (AXIS == 1) ? (int64_t)nx * ny : (int64_t)nx;
+    const int s_ax = (AXIS == 1) ? nx : nx * ny;
+    const int s_b = (AXIS == 1) ? nx * ny : nx;
     const int lx_bits = __builtin_ctz(it.lx);
     int x = it.a + (lane & (it.lx - 1));
     int bb = it.b + (lane >> lx_bits);
-    const bool active = (x < nx) && (bb < nb);
+    M.active = (x < nx) && (bb < nb);
     x = min(x, nx - 1);
     bb = min(bb, nb - 1);
-    const int64_t col = (int64_t)x + (int64_t)bb * s_b;
-    const T* src = reinterpret_cast<const T*>(A.field_base) + ev.off[A.parity] + col;
-    T* dst = reinterpret_cast<T*>(A.field_base) + ev.off[A.parity ^ 1] + col;
-    const int64_t pitch = ev.pitch;
-
-    const double lam = A.lam;
-    const double lamh = 0.5 * lam;
-    const T lamsrc_p = T(-0.25 * lam);   // -lambda'/2 with lambda' = lambda/2
-    const T lamsrc_c = T(-0.5 * lam);    // -lambda'/2 with lambda' = lambda
-    const T diff8 = T(A.diff * 0.125);
-    const bool seg_left = (it.s0 == 0), seg_right = (it.s1 == N);
-
-    FieldPipe<T> F[kNF];
+    M.off_col = (x + bb * s_b) * (int)sizeof(T);
+    M.step_bytes = s_ax * (int)sizeof(T);
+    const int64_t fbytes = ev.ncell * (int64_t)sizeof(T);
+    const T* base = reinterpret_cast<const T*>(A.field_base);
 #pragma unroll
-    for (int q = 0; q < kNF; ++q) pipe_zero(F[q]);
-    // shared windows: predictor (time n) and corrector (time n+1/2)
-    T ep1 = T(0), ep2 = T(0), rdp2 = T(1);   // eps at i-2, i-1; 1/D at (i-2,i-1)
-    T fEp1 = T(0), fEp2 = T(0), fMp1 = T(0), fMp2 = T(0);
-    T ec1 = T(0), ec2 = T(0), rdc2 = T(1);   // eps at i-5, i-4; 1/D at (i-5,i-4)
-    T fEc1 = T(0), fEc2 = T(0), fMc1 = T(0), fMc2 = T(0);
-
-    const int i_lo = it.s0 - kMarchLag, i_hi = it.s1 + kMarchLag;
-    // prefetch queue of two cells
-    T qa[kNF], qb[kNF];
-    {
-      const int64_t o0 = (int64_t)min(max(i_lo, 0), N - 1) * s_ax;
-      const int64_t o1 = (int64_t)min(max(i_lo + 1, 0), N - 1) * s_ax;
-#pragma unroll
-      for (int q = 0; q < kNF; ++q) {
-        qa[q] = src[q * pitch + o0];
-        qb[q] = src[q * pitch + o1];
-      }
+    for (int q = 0; q < kNF; ++q) {
+      M.src[q] = field_rsrc(base + ev.off[A.parity] + q * ev.pitch, fbytes);
+      M.dst[q] = field_rsrc(base + ev.off[A.parity ^ 1] + q * ev.pitch, fbytes);
     }
-    for (int i = i_lo; i < i_hi; ++i) {
-      T un[kNF];
+    M.eos = &A.eos;
+    M.lam = A.lam;
+    M.lamh = 0.5 * A.lam;
+    M.lamsrc_p = T(-0.25 * A.lam);   // -lambda'/2 with lambda' = lambda/2
+    M.lamsrc_c = T(-0.5 * A.lam);    // -lambda'/2 with lambda' = lambda
+    M.diff8 = T(A.diff * 0.125);
+    M.s0 = it.s0;
+    M.s1 = it.s1;
+    M.i_lo = it.s0 - kMarchLag;
 #pragma unroll
-      for (int q = 0; q < kNF; ++q) { un[q] = qa[q]; qa[q] = qb[q]; }
-      {
-        const int64_t o2 = (int64_t)min(max(i + 2, 0), N - 1) * s_ax;
+    for (int j = 0; j < 8; ++j) {
+      M.ep[j] = M.fEp[j] = M.fMp[j] = M.ec[j] = M.fEc[j] = M.fMc[j] = T(0);
+      M.rdp[j] = M.rdc[j] = T(1);
 #pragma unroll
-        for (int q = 0; q < kNF; ++q) qb[q] = src[q * pitch + o2];
-      }
-      // ---- recovery at U^n of cell i
-      const Recovered rn = recover<EOS>(A.eos, double(un[0]), double(un[QP]),
-                                   double(un[QT1]), double(un[QT2]));
-      const double vn = rn.w * double(un[QP]);
-      const T ep_i = T(lamh * vn);
-      const T fE_i = T(rn.p * vn);
-      const T fM_i = T(rn.p);
-      if (active && i >= it.s0 && i < it.s1) {
-        acc[R_CLAMP] += rn.clamped;
-        acc[R_FLOOR] += rn.floored;
-      }
-      // ---- predictor coefficients of cell i-1
-      const T rdp_new = interface_rcp(ep2, ep_i);
-      const Coef<T> kp = coefficients(ep2, rdp2, rdp_new);
-      const T sEp = source(lamsrc_p, fEp1, fE_i);
-      const T sMp = source(lamsrc_p, fMp1, fM_i);
-      // ---- predictor of every field: U^{n+1/2} at cell k = i-3
-      T uh[kNF], d_new[kNF], hp_new[kNF], gp_new[kNF], q_new[kNF], ap_new[kNF];
-#pragma unroll
-      for (int q = 0; q < kNF; ++q) {
-        const T s = (q == 0) ? sEp : ((q == QP) ? sMp : T(0));
-        uh[q] = pipe_predict(F[q], un[q], kp, s, diff8, d_new[q], hp_new[q],
-                             gp_new[q], q_new[q], ap_new[q]);
-      }
-      // ---- recovery at U^{n+1/2} of cell k (halo cells copy the edge cell)
-      const int k = i - 3;
-      T ec_k, fEc_k, fMc_k;
-      if (k < 0) {
-        ec_k = T(0); fEc_k = T(0); fMc_k = T(0);      // replaced at k = 0
-      } else if (k >= N) {
-        ec_k = ec2; fEc_k = fEc2; fMc_k = fMc2;        // copy of cell N-1
-      } else {
-        const Recovered rh = recover<EOS>(A.eos, double(uh[0]), double(uh[QP]),
-                                     double(uh[QT1]), double(uh[QT2]));
-        const double vh = rh.w * double(uh[QP]);
-        ec_k = T(lam * vh);
-        fEc_k = T(rh.p * vh);
-        fMc_k = T(rh.p);
-        if (active && k >= it.s0 && k < it.s1) {
-          acc[R_CLAMP] += rh.clamped;
-          acc[R_FLOOR] += rh.floored;
-          acc[R_MAXEPS] = fmax(acc[R_MAXEPS], fabs(double(ec_k)));
-        }
-      }
-      const bool left_edge = (k == 0);
-      if (left_edge) {
-        ec1 = ec2 = ec_k; fEc1 = fEc2 = fEc_k; fMc1 = fMc2 = fMc_k;
-        rdc2 = interface_rcp(ec1, ec2);
-      }
-      // ---- boundary ledger: flux through the outflow faces (corrector)
-      if (active && ((left_edge && seg_left) || (k == N - 1 && seg_right))) {
-        const double sg = left_edge ? -1.0 : 1.0;
-        const double e64 = double(ec_k);
-#pragma unroll
-        for (int q = 0; q < kNF; ++q) {
-          const double f = (q == 0) ? double(fEc_k) : ((q == QP) ? double(fMc_k) : 0.0);
-          acc[R_LEDGER + q] += sg * face_flux(e64, double(F[q].u2), lam, f);
-        }
-        if (left_edge && k == N - 1) {   // single-cell pencil: both faces
-#pragma unroll
-          for (int q = 0; q < kNF; ++q) {
-            const double f = (q == 0) ? double(fEc_k) : ((q == QP) ? double(fMc_k) : 0.0);
-            acc[R_LEDGER + q] += face_flux(e64, double(F[q].u2), lam, f);
-          }
-        }
-      }
-      // ---- corrector coefficients of cell i-4
-      const T rdc_new = interface_rcp(ec2, ec_k);
-      const Coef<T> kc = coefficients(ec2, rdc2, rdc_new);
-      const T sEc = source(lamsrc_c, fEc1, fEc_k);
-      const T sMc = source(lamsrc_c, fMc1, fMc_k);
-      // ---- corrector of every field: U^{n+1} at cell o = i-6
-      const int o = i - kMarchLag;
-      const bool store = active && (o >= it.s0);
-#pragma unroll
-      for (int q = 0; q < kNF; ++q) {
-        const T s = (q == 0) ? sEc : ((q == QP) ? sMc : T(0));
-        T hc_new, gc_new, ac_new;
-        const T out = pipe_correct(F[q], kc, s, diff8, left_edge, hc_new,
-                                   gc_new, ac_new);
-        if (store) {
-          dst[q * pitch + (int64_t)o * s_ax] = out;
-          acc[R_SUM + q] += double(out);
-        }
-        pipe_shift(F[q], un[q], d_new[q], hp_new[q], gp_new[q], q_new[q],
-                   ap_new[q], hc_new, gc_new, ac_new);
-      }
-      // ---- shift the shared windows
-      ep1 = ep2; ep2 = ep_i; rdp2 = rdp_new;
-      fEp1 = fEp2; fEp2 = fE_i; fMp1 = fMp2; fMp2 = fM_i;
-      ec1 = ec2; ec2 = ec_k; rdc2 = rdc_new;
-      fEc1 = fEc2; fEc2 = fEc_k; fMc1 = fMc2; fMc2 = fMc_k;
+      for (int q = 0; q < kNF; ++q)
+        M.u[q][j] = M.d[q][j] = M.q2[q][j] = M.hp[q][j] = M.gp[q][j] = M.ap[q][j] =
+            M.hc[q][j] = M.gc[q][j] = M.ac[q][j] = T(0);
+    }
+    const int n_it = it.s1 - it.s0 + 2 * kMarchLag;
+    M.template load<0>(M.i_lo);
+    M.template load<1>(M.i_lo + 1);
+    for (int j = 0; j < n_it; j += 8) {
+      const int i = M.i_lo + j;
+      M.template iterate<0>(i);
+      M.template iterate<1>(i + 1);
+      M.template iterate<2>(i + 2);
+      M.template iterate<3>(i + 3);
+      M.template iterate<4>(i + 4);
+      M.template iterate<5>(i + 5);
+      M.template iterate<6>(i + 6);
+      M.template iterate<7>(i + 7);
     }
   }
-  block_record(acc, A.rec);
+  block_record(M.acc, A.rec);
 }
 
 // ------------------------------------------------------------ x sweep
+// A window holds up to 256 positions, 4 consecutive ones per lane.  It covers
+// the cells [c0, c1) of the x-fastest array as row pieces, each preceded and
+// followed by 6 halo positions whose loads are clamped to the row (outflow
+// copy), exactly as the march treats the ends of a pencil.  The stencil then
+// reads plain neighbours (lane-local or from the adjacent lane by a cross-lane
+// shuffle); a position next to another row piece sees unrelated data, which
+// reaches only halo positions (the step has a 6-cell domain of dependence).
+// The only halo rule that is not a plain copy of U^n: at time n+1/2 a halo
+// position takes the velocity and sources of its edge cell (read from LDS).
 template <typename T>
 __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, 64); }
 template <typename T>
 __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, 64); }
 
-// Neighbours of the 4 owned cells: value of cell k-1 / k+1, where cell -1 is
-// the left lane's cell 3 and cell 4 the right lane's cell 0; a cell at the
-// start (end) of its row takes the halo value instead.
 template <typename T>
-__device__ __forceinline__ void neighbours(const T (&v)[kXCells],
-                                           const bool (&isL)[kXCells],
-                                           const bool (&isR)[kXCells],
-                                           const T (&ghostL)[kXCells],
-                                           const T (&ghostR)[kXCells],
-                                           T (&left)[kXCells],
-                                           T (&right)[kXCells]) {
+__device__ __forceinline__ void lr(const T (&v)[kXCells], T (&l)[kXCells], T (&r)[kXCells]) {
   const T vl = from_left(v[kXCells - 1]);
   const T vr = from_right(v[0]);
 #pragma unroll
-  for (int k = 0; k < kXCells; ++k) {
-    const T l = (k > 0) ? v[k - 1] : vl;
-    const T r = (k < kXCells - 1) ? v[k + 1] : vr;
-    left[k] = isL[k] ? ghostL[k] : l;
-    right[k] = isR[k] ? ghostR[k] : r;
+  for (int j = 0; j < kXCells; ++j) {
+    l[j] = (j > 0) ? v[j - 1] : vl;
+    r[j] = (j < kXCells - 1) ? v[j + 1] : vr;
   }
 }
 
-// Same with the halo value equal to the cell's own value (outflow copy).
+// Coefficients and sources of one half step for the 4 owned positions.
 template <typename T>
-__device__ __forceinline__ void neighbours_copy(const T (&v)[kXCells],
-                                                const bool (&isL)[kXCells],
-                                                const bool (&isR)[kXCells],
-                                                T (&left)[kXCells],
-                                                T (&right)[kXCells]) {
-  neighbours(v, isL, isR, v, v, left, right);
-}
-
-// One 1-D SHASTA application to the 4 owned cells of one field along x.
-// u, ul, ur: U and its neighbours (halo applied), dnext: Delta_{k+1};
-// k/kg: coefficients of the cell and of its halo image; s/sg: sources.
-template <typename T>
-__device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCells],
-                                      const T (&ur)[kXCells], const T (&dnext)[kXCells],
-                                      const Coef<T> (&k)[kXCells],
-                                      const Coef<T> (&kg)[kXCells],
-                                      const T (&s)[kXCells], const T (&sg)[kXCells],
-                                      const bool (&isL)[kXCells],
-                                      const bool (&isR)[kXCells], T diff8,
-                                      T (&out)[kXCells]) {
-  T uh[kXCells], ug[kXCells], dh[kXCells], sec[kXCells];
+__device__ __forceinline__ void x_coefficients(const T (&eps)[kXCells], const T (&fE)[kXCells],
+                                               const T (&fM)[kXCells], T lamsrc,
+                                               Coef<T> (&k)[kXCells], T (&sE)[kXCells],
+                                               T (&sM)[kXCells]) {
+  T el[kXCells], er[kXCells], fl[kXCells], fr[kXCells], gl[kXCells], gr[kXCells];
+  lr(eps, el, er);
+  lr(fE, fl, fr);
+  lr(fM, gl, gr);
+  T rdr[kXCells];
+#pragma unroll
+  for (int j = 0; j < kXCells; ++j) rdr[j] = interface_rcp(eps[j], er[j]);
+  const T rl = from_left(rdr[kXCells - 1]);
 #pragma unroll
   for (int j = 0; j < kXCells; ++j) {
-    const T dr = ur[j] - u[j];      // Delta_j
-    const T dl = u[j] - ul[j];      // Delta_{j-1}
-    sec[j] = second_difference(dnext[j], dl, dr);
-    uh[j] = transport(k[j], s[j], dr, dl, u[j]);
-    // halo image of the transported value: all its inputs equal the edge
-    // cell's, so Delta = 0 on both sides and the source vanishes
-    const T z = u[j] - u[j];
-    ug[j] = transport(kg[j], sg[j], z, z, u[j]);
+    k[j] = coefficients(eps[j], (j > 0) ? rdr[j - 1] : rl, rdr[j]);
+    sE[j] = source(lamsrc, fl[j], fr[j]);
+    sM[j] = source(lamsrc, gl[j], gr[j]);
   }
-  // hat Delta_j = hat U_{j+1} - hat U_j
-  T uhr[kXCells];
+}
+
+// One 1-D SHASTA application to the 4 owned positions of one field.
+// u: U^n; ul, ur, ur2: U^n at p-1, p+1, p+2.
+template <typename T>
+__device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCells],
+                                      const T (&ur)[kXCells], const T (&ur2)[kXCells],
+                                      const Coef<T> (&k)[kXCells], const T (&s)[kXCells],
+                                      T diff8, T (&out)[kXCells]) {
+  T uh[kXCells], sec[kXCells];
+#pragma unroll
+  for (int j = 0; j < kXCells; ++j) {
+    const T dr = ur[j] - u[j];       // Delta_p
+    const T dl = u[j] - ul[j];       // Delta_{p-1}
+    const T dn = ur2[j] - ur[j];     // Delta_{p+1}
+    sec[j] = second_difference(dn, dl, dr);
+    uh[j] = transport(k[j], s[j], dr, dl, u[j]);
+  }
+  T dh[kXCells];
   {
     const T r = from_right(uh[0]);
 #pragma unroll
-    for (int j = 0; j < kXCells; ++j)
-      uhr[j] = isR[j] ? ug[j] : ((j < kXCells - 1) ? uh[j + 1] : r);
+    for (int j = 0; j < kXCells; ++j) dh[j] = ((j < kXCells - 1) ? uh[j + 1] : r) - uh[j];
   }
-#pragma unroll
-  for (int j = 0; j < kXCells; ++j) dh[j] = uhr[j] - uh[j];
-  // hat Delta_{j-1}, hat Delta_{j+1}
   T dhl[kXCells], dhr[kXCells];
-  {
-    const T l = from_left(dh[kXCells - 1]);
-    const T r = from_right(dh[0]);
-#pragma unroll
-    for (int j = 0; j < kXCells; ++j) {
-      dhl[j] = isL[j] ? (uh[j] - ug[j]) : ((j > 0) ? dh[j - 1] : l);
-      dhr[j] = isR[j] ? (ug[j] - ug[j]) : ((j < kXCells - 1) ? dh[j + 1] : r);
-    }
-  }
+  lr(dh, dhl, dhr);
   T a[kXCells];
 #pragma unroll
   for (int j = 0; j < kXCells; ++j)
     a[j] = limited_antiflux(dhl[j], dh[j], dhr[j], sec[j], diff8);
-  {
-    const T l = from_left(a[kXCells - 1]);
+  const T al = from_left(a[kXCells - 1]);
 #pragma unroll
-    for (int j = 0; j < kXCells; ++j) {
-      const T al = isL[j] ? T(0) : ((j > 0) ? a[j - 1] : l);
-      out[j] = update(uh[j], a[j], al);
-    }
-  }
-}
-
-// Coefficients and sources of one half step for the 4 owned cells.
-template <typename T>
-__device__ __forceinline__ void x_coefficients(const T (&eps)[kXCells],
-                                               const T (&fE)[kXCells],
-                                               const T (&fM)[kXCells],
-                                               const bool (&isL)[kXCells],
-                                               const bool (&isR)[kXCells],
-                                               T lamsrc, Coef<T> (&k)[kXCells],
-                                               Coef<T> (&kg)[kXCells],
-                                               T (&sE)[kXCells], T (&sM)[kXCells],
-                                               T (&sEg)[kXCells], T (&sMg)[kXCells]) {
-  T el[kXCells], er[kXCells], fl[kXCells], fr[kXCells], gl[kXCells], gr[kXCells];
-  neighbours_copy(eps, isL, isR, el, er);
-  neighbours_copy(fE, isL, isR, fl, fr);
-  neighbours_copy(fM, isL, isR, gl, gr);
-  T rdr[kXCells];
-#pragma unroll
-  for (int j = 0; j < kXCells; ++j) rdr[j] = interface_rcp(eps[j], er[j]);
-  const T rl_lane = from_left(rdr[kXCells - 1]);
-#pragma unroll
-  for (int j = 0; j < kXCells; ++j) {
-    const T one = interface_rcp(eps[j], eps[j]);   // 1/D of a halo interface
-    const T rdl = isL[j] ? one : ((j > 0) ? rdr[j - 1] : rl_lane);
-    k[j] = coefficients(eps[j], rdl, rdr[j]);
-    kg[j] = coefficients(eps[j], one, one);
-    sE[j] = source(lamsrc, fl[j], fr[j]);
-    sM[j] = source(lamsrc, gl[j], gr[j]);
-    sEg[j] = source(lamsrc, fE[j], fE[j]);
-    sMg[j] = source(lamsrc, fM[j], fM[j]);
-  }
+  for (int j = 0; j < kXCells; ++j) out[j] = update(uh[j], a[j], (j > 0) ? a[j - 1] : al);
 }
 
 template <typename T, int EOS>
 __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
   constexpr int QP = 1, QT1 = 2, QT2 = 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int item_id = blockIdx.x * kWavesPerBlock + wave;
+  // wave-uniform: lets the compiler keep the work item in scalar registers
+  const int item_id = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave);
+  __shared__ T halo[kWavesPerBlock][3][kXWindow];
   double acc[13];
 #pragma unroll
   for (int j = 0; j < 13; ++j) acc[j] = 0.0;
@@ -444,120 +398,158 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
     const int nx = ev.n[0];
-    const int ncell = (int)ev.ncell;
     const T* src = reinterpret_cast<const T*>(A.field_base) + ev.off[A.parity];
     T* dst = reinterpret_cast<T*>(A.field_base) + ev.off[A.parity ^ 1];
     const int64_t pitch = ev.pitch;
+    const int2* win = A.xwin + ev.xwin_begin;
     const double lam = A.lam;
     const double lamh = 0.5 * lam;
     const T lamsrc_p = T(-0.25 * lam);
     const T lamsrc_c = T(-0.5 * lam);
     const T diff8 = T(A.diff * 0.125);
+    T* hE = halo[wave][0];
+    T* hF = halo[wave][1];
+    T* hG = halo[wave][2];
 
-    for (int w = 0; w < it.b; ++w) {
-      const int c0 = it.a + w * kXOut;
-      if (c0 >= ncell) break;
-      const int c1 = min(c0 + kXOut, ncell);
-      const int p0 = c0 - kXMargin + kXCells * lane;
-      int pc[kXCells];
-      bool isL[kXCells], isR[kXCells], own[kXCells];
-      {
-        int x = min(max(p0, 0), ncell - 1) % nx;
+    for (int w = it.a; w < it.a + it.b; ++w) {
+      const int2 cw = win[w];
+      const int c0 = cw.x, c1 = cw.y;
+      // ---- map the owned positions to (cell, x) by walking the row pieces
+      int cell[kXCells], xs[kXCells];
+      bool used[kXCells], out_ok[kXCells];
 #pragma unroll
-        for (int j = 0; j < kXCells; ++j) {
-          const int p = p0 + j;
-          pc[j] = min(max(p, 0), ncell - 1);
-          if (j > 0) x = (x + 1 == nx) ? 0 : x + 1;
-          isL[j] = (x == 0);
-          isR[j] = (x == nx - 1);
-          own[j] = (p >= c0) && (p < c1);
+      for (int j = 0; j < kXCells; ++j) {
+        cell[j] = c0; xs[j] = 0; used[j] = false; out_ok[j] = false;
+      }
+      {
+        int ps = 0, c = c0;
+        while (c < c1) {
+          const int row0 = c - (c % nx);            // first cell of the row
+          const int x0 = c - row0;
+          const int len = min(nx - x0, c1 - c);
+#pragma unroll
+          for (int j = 0; j < kXCells; ++j) {
+            const int r = kXCells * lane + j - ps;
+            if (r >= 0 && r < len + 2 * kHalo) {
+              const int x = x0 - kHalo + r;
+              xs[j] = x;
+              cell[j] = row0 + min(max(x, 0), nx - 1);
+              used[j] = true;
+              out_ok[j] = (r >= kHalo) && (r < kHalo + len);
+            }
+          }
+          ps += len + 2 * kHalo;
+          c += len;
         }
       }
       T u[kNF][kXCells];
 #pragma unroll
       for (int q = 0; q < kNF; ++q)
 #pragma unroll
-        for (int j = 0; j < kXCells; ++j) u[q][j] = src[q * pitch + pc[j]];
+        for (int j = 0; j < kXCells; ++j) u[q][j] = src[q * pitch + cell[j]];
 
       // ---- recovery at U^n
       T ep[kXCells], fE[kXCells], fM[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered rn = recover<EOS>(A.eos, double(u[0][j]), double(u[QP][j]),
-                                     double(u[QT1][j]), double(u[QT2][j]));
-        const double v = rn.w * double(u[QP][j]);
+        const Recovered r = recover<EOS>(A.eos, double(u[0][j]), double(u[QP][j]),
+                                         double(u[QT1][j]), double(u[QT2][j]));
+        const double v = r.w * double(u[QP][j]);
         ep[j] = T(lamh * v);
-        fE[j] = T(rn.p * v);
-        fM[j] = T(rn.p);
-        if (own[j]) {
-          acc[R_CLAMP] += rn.clamped;
-          acc[R_FLOOR] += rn.floored;
+        fE[j] = T(r.p * v);
+        fM[j] = T(r.p);
+        if (out_ok[j]) {
+          acc[R_CLAMP] += r.clamped;
+          acc[R_FLOOR] += r.floored;
         }
       }
-      // ---- U^n neighbours (kept for both half steps)
-      T ul[kNF][kXCells], ur[kNF][kXCells], dn[kNF][kXCells];
+      // ---- U^n neighbours p-1, p+1, p+2 (kept for both half steps)
+      T b_l[kNF], b_r0[kNF], b_r1[kNF];
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
-        neighbours_copy(u[q], isL, isR, ul[q], ur[q]);
-        T dr[kXCells];
-#pragma unroll
-        for (int j = 0; j < kXCells; ++j) dr[j] = ur[q][j] - u[q][j];
-        const T r = from_right(dr[0]);
-#pragma unroll
-        for (int j = 0; j < kXCells; ++j)
-          dn[q][j] = isR[j] ? (u[q][j] - u[q][j]) : ((j < kXCells - 1) ? dr[j + 1] : r);
+        b_l[q] = from_left(u[q][kXCells - 1]);
+        b_r0[q] = from_right(u[q][0]);
+        b_r1[q] = from_right(u[q][1]);
       }
       // ---- predictor (lambda/2)
-      Coef<T> k[kXCells], kg[kXCells];
-      T sE[kXCells], sM[kXCells], sEg[kXCells], sMg[kXCells];
-      x_coefficients(ep, fE, fM, isL, isR, lamsrc_p, k, kg, sE, sM, sEg, sMg);
+      Coef<T> k[kXCells];
+      T sE[kXCells], sM[kXCells];
+      x_coefficients(ep, fE, fM, lamsrc_p, k, sE, sM);
       T uh[kNF][kXCells];
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
-        T s[kXCells], sg[kXCells];
+        T ul[kXCells], ur[kXCells], ur2[kXCells], s[kXCells];
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) {
+          ul[j] = (j > 0) ? u[q][j - 1] : b_l[q];
+          ur[j] = (j < kXCells - 1) ? u[q][j + 1] : b_r0[q];
+          ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0[q] : b_r1[q]);
           s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
-          sg[j] = (q == 0) ? sEg[j] : ((q == QP) ? sMg[j] : T(0));
         }
-        x_fct(u[q], ul[q], ur[q], dn[q], k, kg, s, sg, isL, isR, diff8, uh[q]);
+        x_fct(u[q], ul, ur, ur2, k, s, diff8, uh[q]);
       }
-      // ---- recovery at U^{n+1/2}
+      // ---- recovery at U^{n+1/2}; halo positions take their edge cell's
+      //      values (through the wave's LDS table)
       T ec[kXCells], fEc[kXCells], fMc[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered rh = recover<EOS>(A.eos, double(uh[0][j]), double(uh[QP][j]),
-                                     double(uh[QT1][j]), double(uh[QT2][j]));
-        const double v = rh.w * double(uh[QP][j]);
+        const Recovered r = recover<EOS>(A.eos, double(uh[0][j]), double(uh[QP][j]),
+                                         double(uh[QT1][j]), double(uh[QT2][j]));
+        const double v = r.w * double(uh[QP][j]);
         ec[j] = T(lam * v);
-        fEc[j] = T(rh.p * v);
-        fMc[j] = T(rh.p);
-        if (own[j]) {
-          acc[R_CLAMP] += rh.clamped;
-          acc[R_FLOOR] += rh.floored;
+        fEc[j] = T(r.p * v);
+        fMc[j] = T(r.p);
+        if (out_ok[j]) {
+          acc[R_CLAMP] += r.clamped;
+          acc[R_FLOOR] += r.floored;
           acc[R_MAXEPS] = fmax(acc[R_MAXEPS], fabs(double(ec[j])));
         }
+        hE[kXCells * lane + j] = ec[j];
+        hF[kXCells * lane + j] = fEc[j];
+        hG[kXCells * lane + j] = fMc[j];
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int j = 0; j < kXCells; ++j) {
+        const bool ghost = used[j] && (xs[j] < 0 || xs[j] >= nx);
+        if (ghost) {
+          const int pe = kXCells * lane + j + (min(max(xs[j], 0), nx - 1) - xs[j]);
+          ec[j] = hE[pe];
+          fEc[j] = hF[pe];
+          fMc[j] = hG[pe];
+        }
+      }
+      // the table is rewritten by the next window
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // ---- corrector (lambda) from U^n
-      x_coefficients(ec, fEc, fMc, isL, isR, lamsrc_c, k, kg, sE, sM, sEg, sMg);
+      x_coefficients(ec, fEc, fMc, lamsrc_c, k, sE, sM);
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
-        T s[kXCells], sg[kXCells], out[kXCells];
+        T ul[kXCells], ur[kXCells], ur2[kXCells], s[kXCells], out[kXCells];
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) {
+          ul[j] = (j > 0) ? u[q][j - 1] : b_l[q];
+          ur[j] = (j < kXCells - 1) ? u[q][j + 1] : b_r0[q];
+          ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0[q] : b_r1[q]);
           s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
-          sg[j] = (q == 0) ? sEg[j] : ((q == QP) ? sMg[j] : T(0));
         }
-        x_fct(u[q], ul[q], ur[q], dn[q], k, kg, s, sg, isL, isR, diff8, out);
+        x_fct(u[q], ul, ur, ur2, k, s, diff8, out);
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) {
-          if (own[j]) {
-            dst[q * pitch + pc[j]] = out[j];
+          if (out_ok[j]) {
+            dst[q * pitch + cell[j]] = out[j];
             acc[R_SUM + q] += double(out[j]);
-            const double f = (q == 0) ? double(fEc[j]) : ((q == QP) ? double(fMc[j]) : 0.0);
-            const double F = face_flux(double(ec[j]), double(u[q][j]), lam, f);
-            if (isR[j]) acc[R_LEDGER + q] += F;
-            if (isL[j]) acc[R_LEDGER + q] -= F;
+            const bool first = xs[j] == 0, last = xs[j] == nx - 1;
+            if (first || last) {
+              const double f = (q == 0) ? double(fEc[j]) : ((q == QP) ? double(fMc[j]) : 0.0);
+              const double F = face_flux(double(ec[j]), double(u[q][j]), lam, f);
+              if (last) acc[R_LEDGER + q] += F;
+              if (first) acc[R_LEDGER + q] -= F;
+            }
           }
         }
       }
