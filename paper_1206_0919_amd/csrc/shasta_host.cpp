@@ -244,14 +244,16 @@ void build_tables(shasta_t* h) {
               h->items[ax].push_back(it);
             }
       }
-      while ((h->items[ax].size() - start) % kWavesPerBlock) {
+      // x sweep: 4 independent waves per block; y/z: one item per block
+      const int per_block = (ax == 0) ? kWavesPerBlock : 1;
+      while ((h->items[ax].size() - start) % per_block) {
         Item pad{};
         pad.ev = -1;
         pad.lx = 64;
         h->items[ax].push_back(pad);
       }
       d.rec_begin[ax] = rec;
-      d.rec_count[ax] = (int32_t)((h->items[ax].size() - start) / kWavesPerBlock);
+      d.rec_count[ax] = (int32_t)((h->items[ax].size() - start) / per_block);
       rec += d.rec_count[ax];
     }
     h->n_records[ax] = rec;
@@ -276,10 +278,10 @@ void table_capacity(const shasta_t* h, int64_t cap[3], int64_t& rec_cap) {
         for (int lx : {16, 32, 64}) worst = std::max(worst, columns(h, ax, e, lx));
         m = worst * ((N + 15) / 16);
       }
-      n += (m + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
+      n += (ax == 0) ? (m + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock : m;
     }
     cap[ax] = n;
-    rec_cap = std::max(rec_cap, n / kWavesPerBlock);
+    rec_cap = std::max(rec_cap, ax == 0 ? n / kWavesPerBlock : n);
   }
 }
 

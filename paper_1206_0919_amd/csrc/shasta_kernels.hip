@@ -52,8 +52,9 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // acc[0..4] sums, [5..9] ledger, [10] max eps, [11] clamp, [12] floor.
 // Deterministic: fixed butterfly within the wave, fixed wave order.
+template <int NW = kWavesPerBlock>
 __device__ __forceinline__ void block_record(double (&acc)[13], double* rec) {
-  __shared__ double part[kWavesPerBlock][16];
+  __shared__ double part[NW][16];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int j = 0; j < 13; ++j) {
@@ -65,7 +66,7 @@ __device__ __forceinline__ void block_record(double (&acc)[13], double* rec) {
     const int j = threadIdx.x;
     double v = part[0][j];
 #pragma unroll
-    for (int w = 1; w < kWavesPerBlock; ++w)
+    for (int w = 1; w < NW; ++w)
       v = (j == R_MAXEPS) ? fmax(v, part[w][j]) : v + part[w][j];
     rec[(size_t)blockIdx.x * R_SIZE + j] = v;
   }
@@ -94,212 +95,278 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
         __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), v), r, off, 0, 0);
 }
 
-// The march keeps every windowed quantity in a ring of 8 slots: the value of
-// cell p lives in slot (p - i_lo) & 7.  The loop body is instantiated for the
-// 8 phases, so every slot index is a compile-time constant and the windows
-// never move between registers.  At iteration i (cell i of U^n consumed):
-//   predictor: hat U of cell i-1, hat Delta of i-2, antiflux and U^{n+1/2}
-//              of cell i-3;
-//   recovery of U^{n+1/2} at cell i-3;
-//   corrector: hat U of cell i-4, hat Delta of i-5, antiflux and U^{n+1} of
-//              cell i-6.
-// Longest slot lifetime: U^n of a cell is loaded 2 iterations ahead and last
-// used 4 iterations after (7 < 8 slots).
+// The march is split over a pair of waves that work on the same 64 columns:
+//   producer P: loads U^n, recovery at U^n, lambda/2 predictor -> U^{n+1/2};
+//   consumer C: recovery at U^{n+1/2}, lambda corrector from U^n -> U^{n+1},
+//               stores, reductions.
+// P hands U^n (ring of 8 rows) and U^{n+1/2} (ring of 2 rows) to C through
+// LDS; one barrier per iteration keeps C one iteration behind P.  Each wave
+// carries about half of the pipeline state, so two pairs fit on a SIMD.
+//
+// Every windowed quantity lives in a ring of 8 slots: the value of cell p is
+// in slot (p - i_lo) & 7.  The loop body is instantiated for the 8 phases, so
+// slot indices are compile-time constants and windows never move between
+// registers.  At P's iteration i (cell i of U^n consumed): hat U of cell i-1,
+// hat Delta of i-2, antiflux and U^{n+1/2} of cell i-3.  At C's iteration i
+// (one loop trip later): recovery of U^{n+1/2} at i-3, hat U of cell i-4,
+// hat Delta of i-5, antiflux and U^{n+1} of cell i-6.
+template <typename T>
+struct RingLds {
+  T un[8][kNF][64];   // U^n rows, slot (p - i_lo) & 7
+  T uh[2][kNF][64];   // U^{n+1/2} rows, slot = loop trip & 1
+};
+
 template <typename T, int AXIS, int EOS>
-struct March {
+struct MarchCommon {
   static constexpr int QP = 1 + AXIS;            // momentum along the sweep
   static constexpr int QT1 = 1;                  // transverse momenta
   static constexpr int QT2 = (AXIS == 1) ? 3 : 2;
-
-  T u[kNF][8], d[kNF][8], q2[kNF][8];
-  T hp[kNF][8], gp[kNF][8], ap[kNF][8];
-  T hc[kNF][8], gc[kNF][8], ac[kNF][8];
-  T ep[8], fEp[8], fMp[8], rdp[8];
-  T ec[8], fEc[8], fMc[8], rdc[8];
-
-  __amdgpu_buffer_rsrc_t src[kNF], dst[kNF];
-  int off_col;      // byte offset of the lane's column
-  int step_bytes;   // bytes between consecutive cells along the sweep
-  int N, s0, s1, i_lo;
+  int N, s0, s1, lane;
   bool active;
   const EosParams* eos;
   double lam, lamh;
-  T lamsrc_p, lamsrc_c, diff8;
+  T lamsrc, diff8;
   double acc[13];
+};
 
-  __device__ __forceinline__ int off_of(int i) const {
-    return off_col + min(max(i, 0), N - 1) * step_bytes;
+template <typename T, int AXIS, int EOS>
+struct MarchP : MarchCommon<T, AXIS, EOS> {
+  using C = MarchCommon<T, AXIS, EOS>;
+  T u[kNF][8], d[kNF][8], hp[kNF][8], gp[kNF][8], ap[kNF][8];
+  T ep[8], fE[8], fM[8], rd[8];
+  __amdgpu_buffer_rsrc_t src[kNF];
+  int off_col, step_bytes;
+
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ep[j] = fE[j] = fM[j] = T(0);
+      rd[j] = T(1);
+#pragma unroll
+      for (int q = 0; q < kNF; ++q) u[q][j] = d[q][j] = hp[q][j] = gp[q][j] = ap[q][j] = T(0);
+    }
   }
-
   template <int PH>
   __device__ __forceinline__ void load(int i) {
-    const int o = off_of(i);
+    const int o = off_col + min(max(i, 0), this->N - 1) * step_bytes;
 #pragma unroll
     for (int q = 0; q < kNF; ++q) u[q][PH & 7] = buf_load<T>(src[q], o);
   }
-
   template <int PH>
-  __device__ __forceinline__ void iterate(int i) {
+  __device__ __forceinline__ void iterate(int i, RingLds<T>& L, int hslot) {
     constexpr int S0 = PH & 7, S1 = (PH - 1) & 7, S2 = (PH - 2) & 7, S3 = (PH - 3) & 7,
-                  S4 = (PH - 4) & 7, S5 = (PH - 5) & 7, S6 = (PH - 6) & 7, S7 = (PH - 7) & 7;
+                  S4 = (PH - 4) & 7;
+    constexpr int QP = C::QP, QT1 = C::QT1, QT2 = C::QT2;
     load<PH + 2>(i + 2);  // prefetch
-    // ---- recovery at U^n of cell i
+#pragma unroll
+    for (int q = 0; q < kNF; ++q) L.un[S0][q][this->lane] = u[q][S0];
     {
-      const Recovered r = recover<EOS>(*eos, double(u[0][S0]), double(u[QP][S0]),
+      const Recovered r = recover<EOS>(*this->eos, double(u[0][S0]), double(u[QP][S0]),
                                        double(u[QT1][S0]), double(u[QT2][S0]));
       const double v = r.w * double(u[QP][S0]);
-      ep[S0] = T(lamh * v);
-      fEp[S0] = T(r.p * v);
-      fMp[S0] = T(r.p);
-      if (active && i >= s0 && i < s1) {
-        acc[R_CLAMP] += r.clamped;
-        acc[R_FLOOR] += r.floored;
+      ep[S0] = T(this->lamh * v);
+      fE[S0] = T(r.p * v);
+      fM[S0] = T(r.p);
+      if (this->active && i >= this->s0 && i < this->s1) {
+        this->acc[R_CLAMP] += r.clamped;
+        this->acc[R_FLOOR] += r.floored;
       }
     }
-    // ---- predictor of cell i-1 .. U^{n+1/2} of cell i-3
-    rdp[S0] = interface_rcp(ep[S1], ep[S0]);
-    const Coef<T> kp = coefficients(ep[S1], rdp[S1], rdp[S0]);
-    const T sEp = source(lamsrc_p, fEp[S2], fEp[S0]);
-    const T sMp = source(lamsrc_p, fMp[S2], fMp[S0]);
-    T uh[kNF];
+    rd[S0] = interface_rcp(ep[S1], ep[S0]);
+    const Coef<T> kp = coefficients(ep[S1], rd[S1], rd[S0]);
+    const T sE = source(this->lamsrc, fE[S2], fE[S0]);
+    const T sM = source(this->lamsrc, fM[S2], fM[S0]);
 #pragma unroll
     for (int q = 0; q < kNF; ++q) {
-      const T s = (q == 0) ? sEp : ((q == QP) ? sMp : T(0));
+      const T s = (q == 0) ? sE : ((q == QP) ? sM : T(0));
       d[q][S1] = u[q][S0] - u[q][S1];                                    // Delta_{i-1}
       hp[q][S1] = transport(kp, s, d[q][S1], d[q][S2], u[q][S1]);        // hat U_{i-1}
       gp[q][S2] = hp[q][S1] - hp[q][S2];                                 // hat Delta_{i-2}
-      q2[q][S3] = second_difference(d[q][S2], d[q][S4], d[q][S3]);      // at i-3
-      ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], q2[q][S3], diff8);
-      uh[q] = update(hp[q][S3], ap[q][S3], ap[q][S4]);                  // U^{n+1/2}_{i-3}
+      const T sec = second_difference(d[q][S2], d[q][S4], d[q][S3]);    // at i-3
+      ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], sec, this->diff8);
+      L.uh[hslot][q][this->lane] = update(hp[q][S3], ap[q][S3], ap[q][S4]);  // U^{n+1/2}_{i-3}
     }
-    // ---- recovery at U^{n+1/2} of cell k = i-3 (halo cells copy the edge)
+  }
+};
+
+template <typename T, int AXIS, int EOS>
+struct MarchC : MarchCommon<T, AXIS, EOS> {
+  using C = MarchCommon<T, AXIS, EOS>;
+  T u[kNF][8], d[kNF][8], q2[kNF][8], hc[kNF][8], gc[kNF][8], ac[kNF][8];
+  T ec[8], fE[8], fM[8], rd[8];
+  __amdgpu_buffer_rsrc_t dst[kNF];
+  int off_col, step_bytes;
+
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ec[j] = fE[j] = fM[j] = T(0);
+      rd[j] = T(1);
+#pragma unroll
+      for (int q = 0; q < kNF; ++q)
+        u[q][j] = d[q][j] = q2[q][j] = hc[q][j] = gc[q][j] = ac[q][j] = T(0);
+    }
+  }
+  template <int PH>
+  __device__ __forceinline__ void iterate(int i, const RingLds<T>& L, int hslot) {
+    constexpr int S3 = (PH - 3) & 7, S4 = (PH - 4) & 7, S5 = (PH - 5) & 7, S6 = (PH - 6) & 7,
+                  S7 = (PH - 7) & 7;
+    constexpr int QP = C::QP, QT1 = C::QT1, QT2 = C::QT2;
+    const int N = this->N;
+    // ---- receive U^n and U^{n+1/2} of cell k = i-3
+    T uh[kNF];
+#pragma unroll
+    for (int q = 0; q < kNF; ++q) {
+      u[q][S3] = L.un[S3][q][this->lane];
+      uh[q] = L.uh[hslot][q][this->lane];
+      d[q][S4] = u[q][S3] - u[q][S4];                                    // Delta_{i-4}
+      q2[q][S5] = second_difference(d[q][S4], d[q][S6], d[q][S5]);      // at i-5
+    }
+    // ---- recovery at U^{n+1/2} of cell k (halo cells copy the edge cell)
     const int k = i - 3;
     if (k < 0) {
-      ec[S3] = T(0); fEc[S3] = T(0); fMc[S3] = T(0);      // replaced at k = 0
+      ec[S3] = T(0); fE[S3] = T(0); fM[S3] = T(0);      // replaced at k = 0
     } else if (k >= N) {
-      ec[S3] = ec[S4]; fEc[S3] = fEc[S4]; fMc[S3] = fMc[S4];
+      ec[S3] = ec[S4]; fE[S3] = fE[S4]; fM[S3] = fM[S4];
     } else {
-      const Recovered r = recover<EOS>(*eos, double(uh[0]), double(uh[QP]),
+      const Recovered r = recover<EOS>(*this->eos, double(uh[0]), double(uh[QP]),
                                        double(uh[QT1]), double(uh[QT2]));
       const double v = r.w * double(uh[QP]);
-      ec[S3] = T(lam * v);
-      fEc[S3] = T(r.p * v);
-      fMc[S3] = T(r.p);
-      if (active && k >= s0 && k < s1) {
-        acc[R_CLAMP] += r.clamped;
-        acc[R_FLOOR] += r.floored;
-        acc[R_MAXEPS] = fmax(acc[R_MAXEPS], fabs(double(ec[S3])));
+      ec[S3] = T(this->lam * v);
+      fE[S3] = T(r.p * v);
+      fM[S3] = T(r.p);
+      if (this->active && k >= this->s0 && k < this->s1) {
+        this->acc[R_CLAMP] += r.clamped;
+        this->acc[R_FLOOR] += r.floored;
+        this->acc[R_MAXEPS] = fmax(this->acc[R_MAXEPS], fabs(double(ec[S3])));
       }
     }
     const bool left_edge = (k == 0);
     if (left_edge) {
       ec[S4] = ec[S5] = ec[S3];
-      fEc[S4] = fEc[S5] = fEc[S3];
-      fMc[S4] = fMc[S5] = fMc[S3];
-      rdc[S4] = interface_rcp(ec[S5], ec[S4]);
+      fE[S4] = fE[S5] = fE[S3];
+      fM[S4] = fM[S5] = fM[S3];
+      rd[S4] = interface_rcp(ec[S5], ec[S4]);
     }
     // ---- boundary ledger: flux through the outflow faces (corrector)
-    if (active && ((left_edge && s0 == 0) || (k == N - 1 && s1 == N))) {
+    if (this->active && ((left_edge && this->s0 == 0) || (k == N - 1 && this->s1 == N))) {
       const double e64 = double(ec[S3]);
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
-        const double f = (q == 0) ? double(fEc[S3]) : ((q == QP) ? double(fMc[S3]) : 0.0);
-        const double F = face_flux(e64, double(u[q][S3]), lam, f);
-        if (left_edge) acc[R_LEDGER + q] -= F;
-        if (k == N - 1) acc[R_LEDGER + q] += F;
+        const double f = (q == 0) ? double(fE[S3]) : ((q == QP) ? double(fM[S3]) : 0.0);
+        const double F = face_flux(e64, double(u[q][S3]), this->lam, f);
+        if (left_edge) this->acc[R_LEDGER + q] -= F;
+        if (k == N - 1) this->acc[R_LEDGER + q] += F;
       }
     }
     // ---- corrector of cell i-4 .. U^{n+1} of cell o = i-6
-    rdc[S3] = interface_rcp(ec[S4], ec[S3]);
-    const Coef<T> kc = coefficients(ec[S4], rdc[S4], rdc[S3]);
-    const T sEc = source(lamsrc_c, fEc[S5], fEc[S3]);
-    const T sMc = source(lamsrc_c, fMc[S5], fMc[S3]);
+    rd[S3] = interface_rcp(ec[S4], ec[S3]);
+    const Coef<T> kc = coefficients(ec[S4], rd[S4], rd[S3]);
+    const T sE = source(this->lamsrc, fE[S5], fE[S3]);
+    const T sM = source(this->lamsrc, fM[S5], fM[S3]);
     const int o = i - kMarchLag;
-    const bool store = active && o >= s0 && o < s1;
+    const bool store = this->active && o >= this->s0 && o < this->s1;
     const int ooff = off_col + o * step_bytes;
 #pragma unroll
     for (int q = 0; q < kNF; ++q) {
-      const T s = (q == 0) ? sEc : ((q == QP) ? sMc : T(0));
+      const T s = (q == 0) ? sE : ((q == QP) ? sM : T(0));
       hc[q][S4] = transport(kc, s, d[q][S4], d[q][S5], u[q][S4]);       // hat U_{i-4}
       if (left_edge) hc[q][S5] = hc[q][S4];                              // halo: hat U_{-2}
       gc[q][S5] = hc[q][S4] - hc[q][S5];                                 // hat Delta_{i-5}
-      ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], diff8);
+      ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], this->diff8);
       const T out = update(hc[q][S6], ac[q][S6], ac[q][S7]);            // U^{n+1}_{i-6}
       if (store) {
         buf_store<T>(dst[q], ooff, out);
-        acc[R_SUM + q] += double(out);
+        this->acc[R_SUM + q] += double(out);
       }
     }
   }
 };
 
-// AXIS = 1 (y) or 2 (z).
-template <typename T, int AXIS, int EOS>
-__global__ __launch_bounds__(256) void sweep_march(SweepArgs A) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // wave-uniform: lets the compiler keep the work item in scalar registers
-  const int item_id = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave);
-  March<T, AXIS, EOS> M;
+template <typename M>
+__device__ __forceinline__ void march_setup(M& m, const SweepArgs& A, const Item& it,
+                                            const EventDesc& ev, int axis, int lane) {
+  const int nx = ev.n[0], ny = ev.n[1];
+  m.N = ev.n[axis];
+  const int nb = (axis == 1) ? ev.n[2] : ev.n[1];
+  const int s_ax = (axis == 1) ? nx : nx * ny;
+  const int s_b = (axis == 1) ? nx * ny : nx;
+  const int lx_bits = __builtin_ctz(it.lx);
+  int x = it.a + (lane & (it.lx - 1));
+  int bb = it.b + (lane >> lx_bits);
+  m.active = (x < nx) && (bb < nb);
+  x = min(x, nx - 1);
+  bb = min(bb, nb - 1);
+  m.lane = lane;
+  using TT = decltype(m.lamsrc);
+  m.off_col = (x + bb * s_b) * (int)sizeof(TT);
+  m.step_bytes = s_ax * (int)sizeof(TT);
+  m.eos = &A.eos;
+  m.lam = A.lam;
+  m.lamh = 0.5 * A.lam;
+  m.diff8 = TT(A.diff * 0.125);
+  m.s0 = it.s0;
+  m.s1 = it.s1;
 #pragma unroll
-  for (int j = 0; j < 13; ++j) M.acc[j] = 0.0;
+  for (int j = 0; j < 13; ++j) m.acc[j] = 0.0;
+}
 
-  const Item it = A.items[item_id];
+// AXIS = 1 (y) or 2 (z).  Block = one producer/consumer pair = one item.
+template <typename T, int AXIS, int EOS>
+__global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
+  __shared__ RingLds<T> L;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const Item it = A.items[blockIdx.x];
+  double acc[13];
+#pragma unroll
+  for (int j = 0; j < 13; ++j) acc[j] = 0.0;
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
-    const int nx = ev.n[0], ny = ev.n[1];
-    M.N = ev.n[AXIS];
-    const int nb = (AXIS == 1) ? ev.n[2] : ev.n[1];
-    const int s_ax = (AXIS == 1) ? nx : nx * ny;
-    const int s_b = (AXIS == 1) ? nx * ny : nx;
-    const int lx_bits = __builtin_ctz(it.lx);
-    int x = it.a + (lane & (it.lx - 1));
-    int bb = it.b + (lane >> lx_bits);
-    M.active = (x < nx) && (bb < nb);
-    x = min(x, nx - 1);
-    bb = min(bb, nb - 1);
-    M.off_col = (x + bb * s_b) * (int)sizeof(T);
-    M.step_bytes = s_ax * (int)sizeof(T);
     const int64_t fbytes = ev.ncell * (int64_t)sizeof(T);
     const T* base = reinterpret_cast<const T*>(A.field_base);
-#pragma unroll
-    for (int q = 0; q < kNF; ++q) {
-      M.src[q] = field_rsrc(base + ev.off[A.parity] + q * ev.pitch, fbytes);
-      M.dst[q] = field_rsrc(base + ev.off[A.parity ^ 1] + q * ev.pitch, fbytes);
-    }
-    M.eos = &A.eos;
-    M.lam = A.lam;
-    M.lamh = 0.5 * A.lam;
-    M.lamsrc_p = T(-0.25 * A.lam);   // -lambda'/2 with lambda' = lambda/2
-    M.lamsrc_c = T(-0.5 * A.lam);    // -lambda'/2 with lambda' = lambda
-    M.diff8 = T(A.diff * 0.125);
-    M.s0 = it.s0;
-    M.s1 = it.s1;
-    M.i_lo = it.s0 - kMarchLag;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      M.ep[j] = M.fEp[j] = M.fMp[j] = M.ec[j] = M.fEc[j] = M.fMc[j] = T(0);
-      M.rdp[j] = M.rdc[j] = T(1);
+    const int i_lo = it.s0 - kMarchLag;
+    const int trips = it.s1 - it.s0 + 2 * kMarchLag + 1;   // C runs one trip behind
+    if (wave == 0) {
+      MarchP<T, AXIS, EOS> P;
+      march_setup(P, A, it, ev, AXIS, lane);
+      P.lamsrc = T(-0.25 * A.lam);   // -lambda'/2 with lambda' = lambda/2
 #pragma unroll
       for (int q = 0; q < kNF; ++q)
-        M.u[q][j] = M.d[q][j] = M.q2[q][j] = M.hp[q][j] = M.gp[q][j] = M.ap[q][j] =
-            M.hc[q][j] = M.gc[q][j] = M.ac[q][j] = T(0);
-    }
-    const int n_it = it.s1 - it.s0 + 2 * kMarchLag;
-    M.template load<0>(M.i_lo);
-    M.template load<1>(M.i_lo + 1);
-    for (int j = 0; j < n_it; j += 8) {
-      const int i = M.i_lo + j;
-      M.template iterate<0>(i);
-      M.template iterate<1>(i + 1);
-      M.template iterate<2>(i + 2);
-      M.template iterate<3>(i + 3);
-      M.template iterate<4>(i + 4);
-      M.template iterate<5>(i + 5);
-      M.template iterate<6>(i + 6);
-      M.template iterate<7>(i + 7);
+        P.src[q] = field_rsrc(base + ev.off[A.parity] + q * ev.pitch, fbytes);
+      P.init();
+      P.template load<0>(i_lo);
+      P.template load<1>(i_lo + 1);
+      for (int j = 0; j < trips; j += 8) {
+        const int i = i_lo + j;
+#define SHASTA_P(PH) P.template iterate<PH>(i + PH, L, PH & 1); __syncthreads();
+        SHASTA_P(0) SHASTA_P(1) SHASTA_P(2) SHASTA_P(3)
+        SHASTA_P(4) SHASTA_P(5) SHASTA_P(6) SHASTA_P(7)
+#undef SHASTA_P
+      }
+#pragma unroll
+      for (int j = 0; j < 13; ++j) acc[j] = P.acc[j];
+    } else {
+      MarchC<T, AXIS, EOS> Cw;
+      march_setup(Cw, A, it, ev, AXIS, lane);
+      Cw.lamsrc = T(-0.5 * A.lam);   // -lambda'/2 with lambda' = lambda
+#pragma unroll
+      for (int q = 0; q < kNF; ++q)
+        Cw.dst[q] = field_rsrc(base + ev.off[A.parity ^ 1] + q * ev.pitch, fbytes);
+      Cw.init();
+      for (int j = 0; j < trips; j += 8) {
+        // C at trip j handles P's iteration of trip j-1 (virtual cell i-1)
+        const int i = i_lo + j - 1;
+#define SHASTA_C(PH) \
+  if (j + PH > 0) Cw.template iterate<(PH + 7) & 7>(i + PH, L, (PH + 1) & 1); __syncthreads();
+        SHASTA_C(0) SHASTA_C(1) SHASTA_C(2) SHASTA_C(3)
+        SHASTA_C(4) SHASTA_C(5) SHASTA_C(6) SHASTA_C(7)
+#undef SHASTA_C
+      }
+#pragma unroll
+      for (int j = 0; j < 13; ++j) acc[j] = Cw.acc[j];
     }
   }
-  block_record(M.acc, A.rec);
+  block_record<2>(acc, A.rec);
 }
 
 // ------------------------------------------------------------ x sweep
@@ -753,13 +820,13 @@ __global__ void selftest_kernel(const double* in, double* out, int n, int which)
 // ------------------------------------------------------------ launchers
 template <typename T, int EOS>
 hipError_t launch_sweep(int axis, const SweepArgs& a, hipStream_t st) {
-  const dim3 grid(a.n_items / kWavesPerBlock), block(64 * kWavesPerBlock);
   if (axis == 0)
-    hipLaunchKernelGGL((sweep_x<T, EOS>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((sweep_x<T, EOS>), dim3(a.n_items / kWavesPerBlock),
+                       dim3(64 * kWavesPerBlock), 0, st, a);
   else if (axis == 1)
-    hipLaunchKernelGGL((sweep_march<T, 1, EOS>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((sweep_march<T, 1, EOS>), dim3(a.n_items), dim3(128), 0, st, a);
   else
-    hipLaunchKernelGGL((sweep_march<T, 2, EOS>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((sweep_march<T, 2, EOS>), dim3(a.n_items), dim3(128), 0, st, a);
   return hipGetLastError();
 }
 
