@@ -158,10 +158,18 @@ const char* shasta_status_str(int status);
  * is bound it must still be large enough (shasta_workspace_bytes tells).
  */
 int shasta_set_tiles(shasta_t* h, int axis, int p0, int p1);
+
+/* Persistent launch of the sweeps along axis (enable = 1): as many blocks as
+ * fit on the GPU at once take work items (pencil segments or x windows of
+ * every event of the batch) from a queue, largest first, until it is empty.
+ * enable = 0: one block (y, z) or wave (x) per work item.  Results are
+ * bitwise independent of the choice. */
+int shasta_set_persistent(shasta_t* h, int axis, int enable);
 int shasta_get_tiles(const shasta_t* h, int axis, int* p0, int* p1);
 
-/* Time candidate decompositions on the device with the given dt (state is
- * saved and restored), keep the fastest per axis.  Synchronous. */
+/* Time candidate decompositions (tiles and persistent or not) on the device
+ * with the given dt, keep the fastest per axis.  The state is untouched (a
+ * sweep writes only the second buffer).  Synchronous. */
 int shasta_autotune(shasta_t* h, double dt_fm, int reps);
 
 /* Capture the steady-state step cycle (6 steps) in a HIP graph and replay it

@@ -13,7 +13,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "libshasta.so")
+LIB_PATH = os.environ.get("SHASTA_LIB") or os.path.join(HERE, "lib", "libshasta.so")
 
 OK, EINVAL, ESTATE, EWORKSPACE, EHIP, ENONFINITE, ENOCONVERGE = range(7)
 FP64, FP32_MIXED = 0, 1
@@ -48,6 +48,7 @@ _SIGS = {
     "shasta_last_error": ([_h], ctypes.c_char_p),
     "shasta_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "shasta_set_tiles": ([_h, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "shasta_set_persistent": ([_h, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "shasta_get_tiles": ([_h, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "shasta_autotune": ([_h, ctypes.c_double, ctypes.c_int], ctypes.c_int),
@@ -181,6 +182,9 @@ class Shasta:
 
     def set_tiles(self, axis, p0, p1=0):
         _check(self.h, shasta_set_tiles(self.h, axis, p0, p1))
+
+    def set_persistent(self, axis, enable):
+        _check(self.h, shasta_set_persistent(self.h, axis, int(bool(enable))))
 
     def get_tiles(self, axis):
         a, b = ctypes.c_int(), ctypes.c_int()

@@ -17,9 +17,11 @@
 using namespace shasta;
 
 namespace shasta_launch {
-hipError_t sweep(int fp32, int axis, const void* args, hipStream_t st);
+hipError_t sweep(int fp32, int axis, const void* args, int grid, hipStream_t st);
+int resident(int fp32, int eos_kind, int axis);
 hipError_t finalize(const EventDesc* ev, int n_events, const double* const rec[3],
-                    const int axis[3], double* acc, double dt, hipStream_t st);
+                    const int axis[3], double* acc, double dt, int* counters,
+                    hipStream_t st);
 hipError_t write_prim(int fp32, EosParams eos, const double* e, const double* vx,
                       const double* vy, const double* vz, const double* n, void* out,
                       int64_t pitch, int64_t ncell, double* invalid, hipStream_t st);
@@ -50,6 +52,8 @@ struct SweepArgsHost {
   double diff;
   double* rec;
   const int2* xwin;
+  int* counter;
+  const int* order;
   EosParams eos;
 };
 
@@ -76,6 +80,7 @@ struct shasta_handle {
   double diff = 1.0;
 
   // decomposition (0 = automatic per event)
+  bool persistent[3] = {false, false, false};
   int xwin = 0;
   int seg[3] = {0, 0, 0};
   int lanes[3] = {0, 0, 0};
@@ -84,6 +89,7 @@ struct shasta_handle {
   std::vector<EventDesc> evd;
   std::vector<int2> xwins;          // x-sweep windows of all events
   std::vector<Item> items[3];
+  std::vector<int> order[3];        // items by decreasing estimated cost
   int n_records[3] = {0, 0, 0};
   int64_t item_cap[3] = {0, 0, 0};
   int64_t rec_cap = 0;
@@ -91,7 +97,8 @@ struct shasta_handle {
   // workspace layout
   size_t elem = 8;
   size_t field_bytes = 0, off_ev = 0, off_items[3] = {0, 0, 0}, off_rec = 0,
-         off_acc = 0, off_scratch = 0, off_xwin = 0, total = 0;
+         off_acc = 0, off_scratch = 0, off_xwin = 0, off_cnt = 0, off_order[3] = {0, 0, 0},
+         total = 0;
   char* ws = nullptr;
   size_t ws_len = 0;
 
@@ -244,19 +251,22 @@ void build_tables(shasta_t* h) {
               h->items[ax].push_back(it);
             }
       }
-      // x sweep: 4 independent waves per block; y/z: one item per block
-      const int per_block = (ax == 0) ? kWavesPerBlock : 1;
-      while ((h->items[ax].size() - start) % per_block) {
-        Item pad{};
-        pad.ev = -1;
-        pad.lx = 64;
-        h->items[ax].push_back(pad);
-      }
+      // one reduction record per item
       d.rec_begin[ax] = rec;
-      d.rec_count[ax] = (int32_t)((h->items[ax].size() - start) / per_block);
+      d.rec_count[ax] = (int32_t)(h->items[ax].size() - start);
       rec += d.rec_count[ax];
     }
     h->n_records[ax] = rec;
+    // queue order of a persistent launch: largest estimated work first
+    std::vector<double> cost(h->items[ax].size());
+    for (size_t i = 0; i < cost.size(); ++i) {
+      const Item& it = h->items[ax][i];
+      cost[i] = (ax == 0) ? double(it.b) : double(it.s1 - it.s0 + 2 * kMarchLag);
+    }
+    h->order[ax].resize(cost.size());
+    for (size_t i = 0; i < cost.size(); ++i) h->order[ax][i] = (int)i;
+    std::stable_sort(h->order[ax].begin(), h->order[ax].end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
   }
   h->tables_version++;
 }
@@ -278,10 +288,10 @@ void table_capacity(const shasta_t* h, int64_t cap[3], int64_t& rec_cap) {
         for (int lx : {16, 32, 64}) worst = std::max(worst, columns(h, ax, e, lx));
         m = worst * ((N + 15) / 16);
       }
-      n += (ax == 0) ? (m + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock : m;
+      n += m;
     }
     cap[ax] = n;
-    rec_cap = std::max(rec_cap, ax == 0 ? n / kWavesPerBlock : n);
+    rec_cap = std::max(rec_cap, n);
   }
 }
 
@@ -325,6 +335,12 @@ void layout(shasta_t* h) {
   p = align256(p + sizeof(double) * shasta_launch::sum_scratch_doubles());
   h->off_xwin = p;
   p = align256(p + sizeof(int2) * h->xwins.size());
+  h->off_cnt = p;
+  p = align256(p + sizeof(int) * 4);
+  for (int ax = 0; ax < 3; ++ax) {
+    h->off_order[ax] = p;
+    p = align256(p + sizeof(int) * (size_t)h->item_cap[ax]);
+  }
   h->total = p;
 }
 
@@ -348,10 +364,16 @@ int upload_tables(shasta_t* h) {
                              hipMemcpyHostToDevice, h->stream));
   HIPCHECK(h, hipMemcpyAsync(h->ws + h->off_xwin, h->xwins.data(),
                              sizeof(int2) * h->xwins.size(), hipMemcpyHostToDevice, h->stream));
-  for (int ax = 0; ax < 3; ++ax)
+  for (int ax = 0; ax < 3; ++ax) {
     HIPCHECK(h, hipMemcpyAsync(dev_items(h, ax), h->items[ax].data(),
                                sizeof(Item) * h->items[ax].size(), hipMemcpyHostToDevice,
                                h->stream));
+    HIPCHECK(h, hipMemcpyAsync(h->ws + h->off_order[ax], h->order[ax].data(),
+                               sizeof(int) * h->order[ax].size(), hipMemcpyHostToDevice,
+                               h->stream));
+  }
+  // queue counters start at zero (then the step reduction resets them)
+  HIPCHECK(h, shasta_launch::zero(reinterpret_cast<double*>(h->ws + h->off_cnt), 2, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   return SHASTA_OK;
 }
@@ -387,7 +409,19 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
   a.rec = dev_rec(h, slot);
   a.xwin = reinterpret_cast<const int2*>(h->ws + h->off_xwin);
   a.eos = h->eos;
+  a.counter = nullptr;
+  a.order = nullptr;
   if (a.n_items == 0) return SHASTA_OK;
+  const int per_block = (axis == 0) ? kWavesPerBlock : 1;
+  int grid = (a.n_items + per_block - 1) / per_block;
+  if (h->persistent[axis]) {
+    const int res = shasta_launch::resident(h->precision == SHASTA_FP32_MIXED, h->eos.kind, axis);
+    if (res > 0 && res < grid) {
+      grid = res;
+      a.counter = reinterpret_cast<int*>(h->ws + h->off_cnt) + slot;
+      a.order = reinterpret_cast<const int*>(h->ws + h->off_order[axis]);
+    }
+  }
   const bool prof = h->profiling && st == h->stream;
   ProfRec pr{axis, nullptr, nullptr};
   if (prof) {
@@ -396,7 +430,7 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
     if (!pr.a || !pr.b) return fail(h, SHASTA_EHIP, "hipEventCreate failed");
     HIPCHECK(h, hipEventRecord(pr.a, st));
   }
-  HIPCHECK(h, shasta_launch::sweep(h->precision == SHASTA_FP32_MIXED, axis, &a, st));
+  HIPCHECK(h, shasta_launch::sweep(h->precision == SHASTA_FP32_MIXED, axis, &a, grid, st));
   if (prof) {
     HIPCHECK(h, hipEventRecord(pr.b, st));
     h->prof.push_back(pr);
@@ -423,7 +457,7 @@ int enqueue_step(shasta_t* h, int64_t k, int& parity, double dt, hipStream_t st)
     HIPCHECK(h, hipEventRecord(pr.a, st));
   }
   HIPCHECK(h, shasta_launch::finalize(dev_events(h), h->n_events, rec, perm, dev_acc(h, 0),
-                                      dt, st));
+                                      dt, reinterpret_cast<int*>(h->ws + h->off_cnt), st));
   if (prof) {
     HIPCHECK(h, hipEventRecord(pr.b, st));
     h->prof.push_back(pr);
@@ -452,6 +486,10 @@ int capture_cycle(shasta_t* h, double dt) {
   h->graph_parity = h->parity;
   h->graph_version = h->tables_version;
   return SHASTA_OK;
+}
+
+hipError_t reset_counters(shasta_t* h, hipStream_t st) {
+  return shasta_launch::zero(reinterpret_cast<double*>(h->ws + h->off_cnt), 2, st);
 }
 
 int check_ready(shasta_t* h) {
@@ -731,6 +769,14 @@ int shasta_set_tiles(shasta_t* h, int axis, int p0, int p1) {
   return SHASTA_OK;
 }
 
+int shasta_set_persistent(shasta_t* h, int axis, int enable) {
+  if (!h) return SHASTA_EINVAL;
+  if (axis < 0 || axis > 2) return fail(h, SHASTA_EINVAL, "axis must be 0, 1 or 2");
+  h->persistent[axis] = enable != 0;
+  drop_graph(h);
+  return SHASTA_OK;
+}
+
 int shasta_get_tiles(const shasta_t* h, int axis, int* p0, int* p1) {
   if (!h || !p0 || !p1 || axis < 0 || axis > 2) return SHASTA_EINVAL;
   *p0 = axis == 0 ? h->xwin : h->seg[axis];
@@ -754,50 +800,70 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
     for (int ax = 0; ax < 3; ++ax) max_n = std::max(max_n, h->dims[3 * e + ax]);
   auto time_axis = [&](int ax, float& ms) -> int {
     // a sweep reads buffer `parity` and writes the other one, so repeated
-    // sweeps leave the state untouched
-    for (int r = 0; r < 2; ++r)
+    // sweeps leave the state untouched; the queue counter of slot 0 is reset
+    // before every launch (a step does that in its reduction)
+    for (int r = 0; r < 2; ++r) {
+      HIPCHECK(h, reset_counters(h, h->stream));
       if (int rc = launch_sweep(h, ax, h->parity, 0, lam, h->stream)) return rc;
+    }
     HIPCHECK(h, hipEventRecord(a, h->stream));
-    for (int r = 0; r < reps; ++r)
+    for (int r = 0; r < reps; ++r) {
+      HIPCHECK(h, reset_counters(h, h->stream));
       if (int rc = launch_sweep(h, ax, h->parity, 0, lam, h->stream)) return rc;
+    }
     HIPCHECK(h, hipEventRecord(b, h->stream));
     HIPCHECK(h, hipEventSynchronize(b));
     HIPCHECK(h, hipEventElapsedTime(&ms, a, b));
     return SHASTA_OK;
   };
   int rc = SHASTA_OK;
-  // x sweep: windows per wave
+  // x sweep: windows per wave, queue or one wave per item
   {
     float best = 1e30f;
     int best_w = h->xwin;
-    for (int w : {1, 2, 3, 4, 6, 8, 12, 16}) {
-      h->xwin = w;
-      build_tables(h);
-      if ((rc = upload_tables(h))) break;
-      float ms;
-      if ((rc = time_axis(0, ms))) break;
-      if (ms < best) { best = ms; best_w = w; }
-    }
+    bool best_p = h->persistent[0];
+    for (int pers = 0; pers < 2 && rc == SHASTA_OK; ++pers)
+      for (int w : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        h->xwin = w;
+        h->persistent[0] = pers;
+        build_tables(h);
+        if ((rc = upload_tables(h))) break;
+        float ms;
+        if ((rc = time_axis(0, ms))) break;
+        if (ms < best) { best = ms; best_w = w; best_p = pers; }
+      }
     h->xwin = best_w;
+    h->persistent[0] = best_p;
   }
   for (int ax = 1; ax < 3 && rc == SHASTA_OK; ++ax) {
     float best = 1e30f;
     int bs = h->seg[ax], bl = h->lanes[ax];
-    for (int lx : {16, 32, 64}) {
-      for (int L : {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1 << 30}) {
-        if (L != (1 << 30) && L >= max_n) continue;
-        h->seg[ax] = (L == (1 << 30)) ? max_n : L;
-        h->lanes[ax] = lx;
-        build_tables(h);
-        if ((rc = upload_tables(h))) break;
-        float ms;
-        if ((rc = time_axis(ax, ms))) break;
-        if (ms < best) { best = ms; bs = h->seg[ax]; bl = lx; }
+    bool bp = h->persistent[ax];
+    // segment lengths: whole pencils, pencils cut into 2..8 equal parts, and
+    // a few fixed lengths (a segment recomputes a margin of 6 cells per side)
+    std::vector<int> cand;
+    for (int parts = 1; parts <= 8; ++parts) cand.push_back((max_n + parts - 1) / parts);
+    for (int L : {16, 24, 32, 48, 64, 96, 128}) cand.push_back(L);
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int pers = 0; pers < 2 && rc == SHASTA_OK; ++pers)
+      for (int lx : {16, 32, 64}) {
+        for (int L : cand) {
+          if (L < 16 && L < max_n) continue;
+          h->seg[ax] = std::min(L, max_n);
+          h->lanes[ax] = lx;
+          h->persistent[ax] = pers;
+          build_tables(h);
+          if ((rc = upload_tables(h))) break;
+          float ms;
+          if ((rc = time_axis(ax, ms))) break;
+          if (ms < best) { best = ms; bs = h->seg[ax]; bl = lx; bp = pers; }
+        }
+        if (rc) break;
       }
-      if (rc) break;
-    }
     h->seg[ax] = bs;
     h->lanes[ax] = bl;
+    h->persistent[ax] = bp;
   }
   build_tables(h);
   int rc2 = upload_tables(h);

@@ -27,6 +27,13 @@
 
 namespace shasta {
 
+// Rows the producer wave of the march loads ahead of use.
+#ifndef SHASTA_MARCH_PREFETCH
+#define SHASTA_MARCH_PREFETCH 2
+#endif
+constexpr int kPrefetch = SHASTA_MARCH_PREFETCH;
+static_assert(kPrefetch >= 1 && kPrefetch <= 3, "ring of 8 slots: lifetime 4 + prefetch < 8");
+
 struct SweepArgs {
   const EventDesc* ev;
   const Item* items;
@@ -37,6 +44,9 @@ struct SweepArgs {
   double diff;         // antidiffusion scale (1: phoenical)
   double* rec;         // reduction records of this sweep, one per block
   const int2* xwin;    // x sweep: cell range [c0, c1) of every window
+  int* counter;        // persistent launch: next work item (null: one block
+                       // or wave per item, no queue)
+  const int* order;    // persistent launch: items in the order they are taken
   EosParams eos;
 };
 
@@ -51,25 +61,21 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // acc[0..4] sums, [5..9] ledger, [10] max eps, [11] clamp, [12] floor.
-// Deterministic: fixed butterfly within the wave, fixed wave order.
-template <int NW = kWavesPerBlock>
-__device__ __forceinline__ void block_record(double (&acc)[13], double* rec) {
-  __shared__ double part[NW][16];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// One record per work item, written by lane 0: deterministic (fixed
+// butterfly) and independent of which block or wave processed the item.
+__device__ __forceinline__ void wave_record(const double (&acc)[13], double* rec, int item) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int j = 0; j < 13; ++j) {
     const double v = (j == R_MAXEPS) ? wave_max(acc[j]) : wave_sum(acc[j]);
-    if (lane == 0) part[wave][j] = v;
+    if (lane == 0) rec[(size_t)item * R_SIZE + j] = v;
   }
-  __syncthreads();
-  if (threadIdx.x < 13) {
-    const int j = threadIdx.x;
-    double v = part[0][j];
-#pragma unroll
-    for (int w = 1; w < NW; ++w)
-      v = (j == R_MAXEPS) ? fmax(v, part[w][j]) : v + part[w][j];
-    rec[(size_t)blockIdx.x * R_SIZE + j] = v;
-  }
+}
+
+// Work queue of a persistent launch.  The first item of a block (or wave) is
+// its index; the next ones come from an atomic counter in the order table.
+__device__ __forceinline__ int item_at(const SweepArgs& A, int k) {
+  return A.order ? A.order[k] : k;
 }
 
 // ------------------------------------------------------------ march (y, z)
@@ -152,12 +158,13 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
 #pragma unroll
     for (int q = 0; q < kNF; ++q) u[q][PH & 7] = buf_load<T>(src[q], o);
   }
-  template <int PH>
+  // EDGE = false: the caller guarantees that cell i is inside [s0, s1).
+  template <int PH, bool EDGE>
   __device__ __forceinline__ void iterate(int i, RingLds<T>& L, int hslot) {
     constexpr int S0 = PH & 7, S1 = (PH - 1) & 7, S2 = (PH - 2) & 7, S3 = (PH - 3) & 7,
                   S4 = (PH - 4) & 7;
     constexpr int QP = C::QP, QT1 = C::QT1, QT2 = C::QT2;
-    load<PH + 2>(i + 2);  // prefetch
+    load<PH + kPrefetch>(i + kPrefetch);  // prefetch
 #pragma unroll
     for (int q = 0; q < kNF; ++q) L.un[S0][q][this->lane] = u[q][S0];
     {
@@ -167,7 +174,7 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
       ep[S0] = T(this->lamh * v);
       fE[S0] = T(r.p * v);
       fM[S0] = T(r.p);
-      if (this->active && i >= this->s0 && i < this->s1) {
+      if (this->active && (!EDGE || (i >= this->s0 && i < this->s1))) {
         this->acc[R_CLAMP] += r.clamped;
         this->acc[R_FLOOR] += r.floored;
       }
@@ -207,7 +214,9 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
         u[q][j] = d[q][j] = q2[q][j] = hc[q][j] = gc[q][j] = ac[q][j] = T(0);
     }
   }
-  template <int PH>
+  // EDGE = false: the caller guarantees 1 <= k <= N-2, k and o inside
+  // [s0, s1) (no pencil end, no halo rule, every result is stored).
+  template <int PH, bool EDGE>
   __device__ __forceinline__ void iterate(int i, const RingLds<T>& L, int hslot) {
     constexpr int S3 = (PH - 3) & 7, S4 = (PH - 4) & 7, S5 = (PH - 5) & 7, S6 = (PH - 6) & 7,
                   S7 = (PH - 7) & 7;
@@ -224,9 +233,9 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
     }
     // ---- recovery at U^{n+1/2} of cell k (halo cells copy the edge cell)
     const int k = i - 3;
-    if (k < 0) {
+    if (EDGE && k < 0) {
       ec[S3] = T(0); fE[S3] = T(0); fM[S3] = T(0);      // replaced at k = 0
-    } else if (k >= N) {
+    } else if (EDGE && k >= N) {
       ec[S3] = ec[S4]; fE[S3] = fE[S4]; fM[S3] = fM[S4];
     } else {
       const Recovered r = recover<EOS>(*this->eos, double(uh[0]), double(uh[QP]),
@@ -235,21 +244,21 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       ec[S3] = T(this->lam * v);
       fE[S3] = T(r.p * v);
       fM[S3] = T(r.p);
-      if (this->active && k >= this->s0 && k < this->s1) {
+      if (this->active && (!EDGE || (k >= this->s0 && k < this->s1))) {
         this->acc[R_CLAMP] += r.clamped;
         this->acc[R_FLOOR] += r.floored;
         this->acc[R_MAXEPS] = fmax(this->acc[R_MAXEPS], fabs(double(ec[S3])));
       }
     }
-    const bool left_edge = (k == 0);
-    if (left_edge) {
+    const bool left_edge = EDGE && (k == 0);
+    if (EDGE && left_edge) {
       ec[S4] = ec[S5] = ec[S3];
       fE[S4] = fE[S5] = fE[S3];
       fM[S4] = fM[S5] = fM[S3];
       rd[S4] = interface_rcp(ec[S5], ec[S4]);
     }
     // ---- boundary ledger: flux through the outflow faces (corrector)
-    if (this->active && ((left_edge && this->s0 == 0) || (k == N - 1 && this->s1 == N))) {
+    if (EDGE && this->active && ((left_edge && this->s0 == 0) || (k == N - 1 && this->s1 == N))) {
       const double e64 = double(ec[S3]);
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
@@ -265,13 +274,13 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
     const T sE = source(this->lamsrc, fE[S5], fE[S3]);
     const T sM = source(this->lamsrc, fM[S5], fM[S3]);
     const int o = i - kMarchLag;
-    const bool store = this->active && o >= this->s0 && o < this->s1;
+    const bool store = this->active && (!EDGE || (o >= this->s0 && o < this->s1));
     const int ooff = off_col + o * step_bytes;
 #pragma unroll
     for (int q = 0; q < kNF; ++q) {
       const T s = (q == 0) ? sE : ((q == QP) ? sM : T(0));
       hc[q][S4] = transport(kc, s, d[q][S4], d[q][S5], u[q][S4]);       // hat U_{i-4}
-      if (left_edge) hc[q][S5] = hc[q][S4];                              // halo: hat U_{-2}
+      if (EDGE && left_edge) hc[q][S5] = hc[q][S4];                      // halo: hat U_{-2}
       gc[q][S5] = hc[q][S4] - hc[q][S5];                                 // hat Delta_{i-5}
       ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], this->diff8);
       const T out = update(hc[q][S6], ac[q][S6], ac[q][S7]);            // U^{n+1}_{i-6}
@@ -311,12 +320,19 @@ __device__ __forceinline__ void march_setup(M& m, const SweepArgs& A, const Item
   for (int j = 0; j < 13; ++j) m.acc[j] = 0.0;
 }
 
-// AXIS = 1 (y) or 2 (z).  Block = one producer/consumer pair = one item.
-template <typename T, int AXIS, int EOS>
+// AXIS = 1 (y) or 2 (z).  Block = one producer/consumer pair; it processes
+// one work item, or, in a persistent launch, items from the queue until the
+// queue is empty.
+template <typename T, int AXIS, int EOS, bool PERSIST>
 __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
   __shared__ RingLds<T> L;
+  __shared__ double part[16];
+  __shared__ int next;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Item it = A.items[blockIdx.x];
+  for (int k = blockIdx.x; k < A.n_items;) {
+  // wave-uniform: keeps the work item and the buffer descriptors scalar
+  const int item = __builtin_amdgcn_readfirstlane(item_at(A, k));
+  const Item it = A.items[item];
   double acc[13];
 #pragma unroll
   for (int j = 0; j < 13; ++j) acc[j] = 0.0;
@@ -326,6 +342,18 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
     const T* base = reinterpret_cast<const T*>(A.field_base);
     const int i_lo = it.s0 - kMarchLag;
     const int trips = it.s1 - it.s0 + 2 * kMarchLag + 1;   // C runs one trip behind
+    const int N = ev.n[AXIS];
+    // A chunk of 8 trips is "interior" when no trip of either wave meets a
+    // pencil end, a halo rule or a cell outside the written segment.
+    // P at trip t handles cell i = i_lo + t; C handles k = i_lo + t - 4 and
+    // o = i_lo + t - 7.
+    auto interior = [&](int j) {
+      const int iP0 = i_lo + j, iP1 = i_lo + j + 7;
+      const int k0 = i_lo + j - 4, k1 = i_lo + j + 3;
+      const int o0 = i_lo + j - 7, o1 = i_lo + j;
+      return j >= 1 && iP0 >= it.s0 && iP1 < it.s1 && k0 >= 1 &&
+             k1 <= N - 2 && k0 >= it.s0 && k1 < it.s1 && o0 >= it.s0 && o1 < it.s1;
+    };
     if (wave == 0) {
       MarchP<T, AXIS, EOS> P;
       march_setup(P, A, it, ev, AXIS, lane);
@@ -335,14 +363,21 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
         P.src[q] = field_rsrc(base + ev.off[A.parity] + q * ev.pitch, fbytes);
       P.init();
       P.template load<0>(i_lo);
-      P.template load<1>(i_lo + 1);
-      for (int j = 0; j < trips; j += 8) {
-        const int i = i_lo + j;
-#define SHASTA_P(PH) P.template iterate<PH>(i + PH, L, PH & 1); __syncthreads();
-        SHASTA_P(0) SHASTA_P(1) SHASTA_P(2) SHASTA_P(3)
-        SHASTA_P(4) SHASTA_P(5) SHASTA_P(6) SHASTA_P(7)
+      if constexpr (kPrefetch >= 2) P.template load<1>(i_lo + 1);
+      if constexpr (kPrefetch >= 3) P.template load<2>(i_lo + 2);
+#define SHASTA_P(PH, E) P.template iterate<PH, E>(i + PH, L, PH & 1); __syncthreads();
+#define SHASTA_P8(E)                                                           \
+  {                                                                            \
+    const int i = i_lo + j;                                                    \
+    SHASTA_P(0, E) SHASTA_P(1, E) SHASTA_P(2, E) SHASTA_P(3, E)                \
+    SHASTA_P(4, E) SHASTA_P(5, E) SHASTA_P(6, E) SHASTA_P(7, E)                \
+  }
+      int j = 0;
+      for (; j < trips && !interior(j); j += 8) SHASTA_P8(true)
+      for (; j < trips && interior(j); j += 8) SHASTA_P8(false)
+      for (; j < trips; j += 8) SHASTA_P8(true)
+#undef SHASTA_P8
 #undef SHASTA_P
-      }
 #pragma unroll
       for (int j = 0; j < 13; ++j) acc[j] = P.acc[j];
     } else {
@@ -353,20 +388,46 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
       for (int q = 0; q < kNF; ++q)
         Cw.dst[q] = field_rsrc(base + ev.off[A.parity ^ 1] + q * ev.pitch, fbytes);
       Cw.init();
-      for (int j = 0; j < trips; j += 8) {
-        // C at trip j handles P's iteration of trip j-1 (virtual cell i-1)
-        const int i = i_lo + j - 1;
-#define SHASTA_C(PH) \
-  if (j + PH > 0) Cw.template iterate<(PH + 7) & 7>(i + PH, L, (PH + 1) & 1); __syncthreads();
-        SHASTA_C(0) SHASTA_C(1) SHASTA_C(2) SHASTA_C(3)
-        SHASTA_C(4) SHASTA_C(5) SHASTA_C(6) SHASTA_C(7)
+      // C at trip j handles P's iteration of trip j-1 (virtual cell i-1)
+#define SHASTA_C(PH, E)                                                            \
+  if (E == false || j + PH > 0)                                                    \
+    Cw.template iterate<(PH + 7) & 7, E>(i + PH, L, (PH + 1) & 1);                 \
+  __syncthreads();
+#define SHASTA_C8(E)                                                               \
+  {                                                                                \
+    const int i = i_lo + j - 1;                                                    \
+    SHASTA_C(0, E) SHASTA_C(1, E) SHASTA_C(2, E) SHASTA_C(3, E)                    \
+    SHASTA_C(4, E) SHASTA_C(5, E) SHASTA_C(6, E) SHASTA_C(7, E)                    \
+  }
+      int j = 0;
+      for (; j < trips && !interior(j); j += 8) SHASTA_C8(true)
+      for (; j < trips && interior(j); j += 8) SHASTA_C8(false)
+      for (; j < trips; j += 8) SHASTA_C8(true)
+#undef SHASTA_C8
 #undef SHASTA_C
-      }
 #pragma unroll
       for (int j = 0; j < 13; ++j) acc[j] = Cw.acc[j];
     }
   }
-  block_record<2>(acc, A.rec);
+  // one record per item: consumer and producer parts summed in a fixed order
+  {
+    double v[13];
+#pragma unroll
+    for (int j = 0; j < 13; ++j) v[j] = (j == R_MAXEPS) ? wave_max(acc[j]) : wave_sum(acc[j]);
+    if (wave == 1 && lane == 0)
+      for (int j = 0; j < 13; ++j) part[j] = v[j];
+    __syncthreads();
+    if (wave == 0 && lane == 0) {
+      for (int j = 0; j < 13; ++j)
+        A.rec[(size_t)item * R_SIZE + j] = (j == R_MAXEPS) ? fmax(v[j], part[j]) : v[j] + part[j];
+      if (PERSIST) next = atomicAdd(A.counter, 1) + (int)gridDim.x;
+    }
+    if (!PERSIST) break;
+    __syncthreads();
+    k = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+  }
+  }
 }
 
 // ------------------------------------------------------------ x sweep
@@ -450,18 +511,19 @@ __device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCel
   for (int j = 0; j < kXCells; ++j) out[j] = update(uh[j], a[j], (j > 0) ? a[j - 1] : al);
 }
 
-template <typename T, int EOS>
+template <typename T, int EOS, bool PERSIST>
 __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
   constexpr int QP = 1, QT1 = 2, QT2 = 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // wave-uniform: lets the compiler keep the work item in scalar registers
-  const int item_id = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave);
   __shared__ T halo[kWavesPerBlock][3][kXWindow];
+  // wave-uniform: lets the compiler keep the work item in scalar registers
+  for (int kq = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave);
+       kq < A.n_items;) {
+  const int item = __builtin_amdgcn_readfirstlane(item_at(A, kq));
+  const Item it = A.items[item];
   double acc[13];
 #pragma unroll
   for (int j = 0; j < 13; ++j) acc[j] = 0.0;
-
-  const Item it = A.items[item_id];
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
     const int nx = ev.n[0];
@@ -622,7 +684,12 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
       }
     }
   }
-  block_record(acc, A.rec);
+  wave_record(acc, A.rec, item);
+  if (!PERSIST) break;
+  int nk = 0;
+  if (lane == 0) nk = atomicAdd(A.counter, 1) + (int)gridDim.x * kWavesPerBlock;
+  kq = __builtin_amdgcn_readfirstlane(__shfl(nk, 0, 64));
+  }
 }
 
 // ------------------------------------------------------------ step reduction
@@ -634,11 +701,13 @@ struct FinalizeArgs {
   int axis[3];
   double* acc;     // A_SIZE doubles per event
   double dt;
+  int* counters;   // queue counters of the three sweeps, reset for the next step
 };
 
 __global__ __launch_bounds__(256) void finalize_step(FinalizeArgs F) {
   const EventDesc& ev = F.ev[blockIdx.x];
   __shared__ double red[256][13];
+  if (blockIdx.x == 0 && threadIdx.x < 3) F.counters[threadIdx.x] = 0;
   double v[13];
 #pragma unroll
   for (int j = 0; j < 13; ++j) v[j] = 0.0;
@@ -818,16 +887,34 @@ __global__ void selftest_kernel(const double* in, double* out, int n, int which)
 }
 
 // ------------------------------------------------------------ launchers
-template <typename T, int EOS>
-hipError_t launch_sweep(int axis, const SweepArgs& a, hipStream_t st) {
+template <typename T, int EOS, bool P>
+hipError_t launch_sweep(int axis, const SweepArgs& a, int grid, hipStream_t st) {
   if (axis == 0)
-    hipLaunchKernelGGL((sweep_x<T, EOS>), dim3(a.n_items / kWavesPerBlock),
-                       dim3(64 * kWavesPerBlock), 0, st, a);
+    hipLaunchKernelGGL((sweep_x<T, EOS, P>), dim3(grid), dim3(64 * kWavesPerBlock), 0, st, a);
   else if (axis == 1)
-    hipLaunchKernelGGL((sweep_march<T, 1, EOS>), dim3(a.n_items), dim3(128), 0, st, a);
+    hipLaunchKernelGGL((sweep_march<T, 1, EOS, P>), dim3(grid), dim3(128), 0, st, a);
   else
-    hipLaunchKernelGGL((sweep_march<T, 2, EOS>), dim3(a.n_items), dim3(128), 0, st, a);
+    hipLaunchKernelGGL((sweep_march<T, 2, EOS, P>), dim3(grid), dim3(128), 0, st, a);
   return hipGetLastError();
+}
+
+// Blocks of the persistent sweep kernel that fit on the whole GPU at once.
+template <typename T, int EOS>
+int resident_blocks(int axis) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e;
+  if (axis == 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sweep_x<T, EOS, true>,
+                                                     64 * kWavesPerBlock, 0);
+  else if (axis == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sweep_march<T, 1, EOS, true>, 128, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sweep_march<T, 2, EOS, true>, 128, 0);
+  if (e != hipSuccess) return 0;
+  return per * cus;
 }
 
 }  // namespace shasta
@@ -836,16 +923,34 @@ hipError_t launch_sweep(int axis, const SweepArgs& a, hipStream_t st) {
 namespace shasta_launch {
 using namespace shasta;
 
-hipError_t sweep(int fp32, int axis, const void* args, hipStream_t st) {
+hipError_t sweep(int fp32, int axis, const void* args, int grid, hipStream_t st) {
   const SweepArgs& a = *static_cast<const SweepArgs*>(args);
-  if (a.eos.kind == 0)
-    return fp32 ? launch_sweep<float, 0>(axis, a, st) : launch_sweep<double, 0>(axis, a, st);
-  return fp32 ? launch_sweep<float, 1>(axis, a, st) : launch_sweep<double, 1>(axis, a, st);
+  const bool p = a.counter != nullptr;
+  if (a.eos.kind == 0) {
+    if (fp32)
+      return p ? launch_sweep<float, 0, true>(axis, a, grid, st)
+               : launch_sweep<float, 0, false>(axis, a, grid, st);
+    return p ? launch_sweep<double, 0, true>(axis, a, grid, st)
+             : launch_sweep<double, 0, false>(axis, a, grid, st);
+  }
+  if (fp32)
+    return p ? launch_sweep<float, 1, true>(axis, a, grid, st)
+             : launch_sweep<float, 1, false>(axis, a, grid, st);
+  return p ? launch_sweep<double, 1, true>(axis, a, grid, st)
+           : launch_sweep<double, 1, false>(axis, a, grid, st);
+}
+
+int resident(int fp32, int eos_kind, int axis) {
+  if (eos_kind == 0)
+    return fp32 ? resident_blocks<float, 0>(axis) : resident_blocks<double, 0>(axis);
+  return fp32 ? resident_blocks<float, 1>(axis) : resident_blocks<double, 1>(axis);
 }
 
 hipError_t finalize(const EventDesc* ev, int n_events, const double* const rec[3],
-                    const int axis[3], double* acc, double dt, hipStream_t st) {
+                    const int axis[3], double* acc, double dt, int* counters,
+                    hipStream_t st) {
   FinalizeArgs f;
+  f.counters = counters;
   f.ev = ev;
   for (int s = 0; s < 3; ++s) { f.rec[s] = rec[s]; f.axis[s] = axis[s]; }
   f.acc = acc;

@@ -18,12 +18,16 @@ def _find(d, pattern):
 
 
 def short(name):
-    for key in ("sweep_x", "sweep_march", "finalize_step", "stream_copy", "prim_to_cons",
-                "read_out", "sum_fields", "combine_sums", "zero_doubles", "cons_in"):
+    """Readable kernel name: sweep_x / sweep_y / sweep_z plus template flags."""
+    if "sweep_march" in name:
+        axis = "y" if "Li1E" in name.split("sweep_march", 1)[1][:12] else "z"
+        return f"sweep_{axis}" + ("<f32>" if "IfLi" in name else "<f64>")
+    if "sweep_x" in name:
+        return "sweep_x" + ("<f32>" if "sweep_xIf" in name else "<f64>")
+    for key in ("finalize_step", "stream_copy", "prim_to_cons", "read_out", "sum_fields",
+                "combine_sums", "zero_doubles", "cons_in"):
         if key in name:
-            tail = name.split(key, 1)[1]
-            args = tail[tail.find("I") + 1:tail.find("EE")] if "I" in tail[:3] else ""
-            return key + (f"<{args}>" if args else "")
+            return key
     return name[:60]
 
 
@@ -67,9 +71,49 @@ def pmc(d, counters=None):
             print(f"| {name} | {cname} | {len(per)} | {avg:.6g} |")
 
 
+def per_dispatch(d, counter):
+    """Average value of one counter per dispatch, per kernel."""
+    files = _find(d, "*counter_collection.csv")
+    acc = defaultdict(lambda: defaultdict(float))
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = short(r.get("Kernel_Name", "?"))
+            acc[name][r.get("Dispatch_Id", "0")] += float(r["Counter_Value"])
+    return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+
+def traffic(fetch_dir, write_dir, workload, fetch_scale, write_scale, out_dir):
+    """Write profiles/traffic_<kernel>_<workload>.json: HBM bytes per launch
+    = fetch_scale * FETCH_SIZE + write_scale * WRITE_SIZE (KiB), tagged with
+    the hash of the kernel sources they were measured on."""
+    import json
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from bench import kernel_source_hash
+    fe = per_dispatch(fetch_dir, "FETCH_SIZE")
+    wr = per_dispatch(write_dir, "WRITE_SIZE")
+    for k in fe:
+        if not k.startswith("sweep") or k not in wr:
+            continue
+        base = k.split("<")[0]
+        rec = {"kernel": k, "workload": workload, "fetch_KiB": fe[k], "write_KiB": wr[k],
+               "fetch_scale": fetch_scale, "write_scale": write_scale,
+               "bytes_per_launch": 1024 * (fetch_scale * fe[k] + write_scale * wr[k]),
+               "source_hash": kernel_source_hash()}
+        path = os.path.join(out_dir, f"traffic_{base}_{workload}.json")
+        with open(path, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(path, rec["bytes_per_launch"])
+
+
 if __name__ == "__main__":
-    mode, d = sys.argv[1], sys.argv[2]
+    mode = sys.argv[1]
     if mode == "stats":
-        stats(d)
+        stats(sys.argv[2])
+    elif mode == "traffic":
+        # traffic FETCH_DIR WRITE_DIR WORKLOAD FETCH_SCALE WRITE_SCALE OUT_DIR
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),
+                float(sys.argv[6]), sys.argv[7])
     else:
-        pmc(d, sys.argv[3:] or None)
+        pmc(sys.argv[2], sys.argv[3:] or None)

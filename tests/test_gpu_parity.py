@@ -211,13 +211,15 @@ def test_decomposition_does_not_change_results(B, torch):
     v = rng.uniform(-0.3, 0.3, (3,) + pr.e.shape)
     prim = inputs.Primitive(pr.e, v[0], v[1], v[2], pr.n)
     outs = []
-    for tiles in ([(0, 1, 0), (1, 16, 16), (2, 16, 64)],
-                  [(0, 3, 0), (1, 24, 32), (2, 40, 16)],
-                  [(0, 0, 0), (1, 0, 0), (2, 0, 0)],
-                  [(0, 16, 0), (1, 66, 64), (2, 50, 32)]):
+    for tiles, pers in (([(0, 1, 0), (1, 16, 16), (2, 16, 64)], (0, 0, 0)),
+                        ([(0, 3, 0), (1, 24, 32), (2, 40, 16)], (1, 1, 1)),
+                        ([(0, 0, 0), (1, 0, 0), (2, 0, 0)], (0, 1, 0)),
+                        ([(0, 16, 0), (1, 66, 64), (2, 50, 32)], (1, 0, 1))):
         s = gpu_state(B, torch, prim)
         for t in tiles:
             s.set_tiles(*t)
+        for ax, p in enumerate(pers):
+            s.set_persistent(ax, p)
         s.step(DT, 6)
         outs.append(read_np(s))
     for o in outs[1:]:
@@ -297,6 +299,8 @@ def test_batched_equals_single_events(B, torch):
         sb = B.Shasta(dims, DX, precision=prec)
         for k, pr in enumerate(prims):
             sb.write_primitive(k, *[torch.from_numpy(a) for a in pr.as_tuple()])
+        for ax in range(3):            # one persistent launch per sweep
+            sb.set_persistent(ax, True)
         sb.step(DT, 8)
         for k, pr in enumerate(prims):
             s1 = gpu_state(B, torch, pr, precision=prec)
