@@ -119,17 +119,32 @@ def cpu_baseline(wl, prims, budget_s=20.0):
                        f"of the FP64 oracle, OpenMP over pencils, {cores} threads, {t:.1f}s")
 
 
-def run_workload(torch, B, name, steps, warmup, autotune=True, profile_steps=12):
+def parse_tiles(text):
+    """'p0,p1,pers/p0,p1,pers/p0,p1,pers' (x/y/z) -> list of triples."""
+    dec = [tuple(int(v) for v in part.split(",")) for part in text.split("/")]
+    if len(dec) != 3 or any(len(t) != 3 for t in dec):
+        raise SystemExit("--tiles wants three p0,p1,persistent triples separated by '/'")
+    return dec
+
+
+def format_tiles(dec):
+    return "/".join(",".join(str(v) for v in t) for t in dec)
+
+
+def run_workload(torch, B, name, steps, warmup, autotune=True, profile_steps=12, tiles=None):
     from paper_1206_0919_amd import inputs
     wl = inputs.workload(name)
     precision = B.FP32_MIXED if wl["precision"] == "fp32" else B.FP64
     s, prims, cells = make_state(torch, B, wl, precision)
     dt = wl["lam"] * wl["dx"]
-    if autotune:
+    if tiles is not None:
+        s.set_decomposition(tiles)
+    elif autotune:
+        s.step(dt, warmup)   # clocks up before the candidates are timed
         t0 = time.time()
-        s.autotune(dt, 3)
+        s.autotune(dt, 4)
         log(f"{name}: autotuned in {time.time() - t0:.1f}s: "
-            + ", ".join(f"axis{a}={s.get_tiles(a)}" for a in range(3)))
+            + format_tiles(s.decomposition()))
     s.step(dt, warmup)
     torch.cuda.synchronize()
     log(f"{name}: warmup {warmup} steps done; timing {steps} steps")
@@ -148,6 +163,10 @@ def main():
                     help="also measure the FP32 and batched workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tiles", default=None,
+                    help="fixed decomposition 'p0,p1,persistent' for x/y/z separated "
+                         "by '/' (as printed in the JSON line's 'decomposition'); "
+                         "skips the autotuner")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -159,7 +178,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     s, prims, wl, cells, ms, prof, precision = run_workload(
-        torch, B, args.workload, args.steps, args.warmup, not args.no_autotune)
+        torch, B, args.workload, args.steps, args.warmup, not args.no_autotune,
+        tiles=parse_tiles(args.tiles) if args.tiles else None)
     value = cells * args.steps / (ms / 1000.0)
     esize = 8 if precision == B.FP64 else 4
     # dominant kernel: the sweep class with the largest total time
@@ -193,6 +213,7 @@ def main():
                      "bytes_per_launch": per_launch},
         "step_hbm_frac": value * (step_bytes / cells) / (HBM_PEAK_GBS * 1e9),
         "kernels": prof,
+        "decomposition": format_tiles(s.decomposition()),
     }
     red = s.reduce(0)
     rec["check"] = {"nonfinite": red["nonfinite"], "clamp": red["clamp"],

@@ -165,11 +165,17 @@ int shasta_set_tiles(shasta_t* h, int axis, int p0, int p1);
  * enable = 0: one block (y, z) or wave (x) per work item.  Results are
  * bitwise independent of the choice. */
 int shasta_set_persistent(shasta_t* h, int axis, int enable);
+
+/* Current decomposition of axis: p0, p1 as for shasta_set_tiles, and 1 if
+ * its sweeps use the persistent launch.  EINVAL for a bad axis or a null
+ * output pointer. */
 int shasta_get_tiles(const shasta_t* h, int axis, int* p0, int* p1);
+int shasta_get_persistent(const shasta_t* h, int axis, int* enable);
 
 /* Time candidate decompositions (tiles and persistent or not) on the device
- * with the given dt, keep the fastest per axis.  The state is untouched (a
- * sweep writes only the second buffer).  Synchronous. */
+ * with the given dt, keep the fastest per axis.  A candidate's time is the
+ * fastest of three blocks of reps sweeps.  The state is untouched (a sweep
+ * writes only the second buffer).  Synchronous. */
 int shasta_autotune(shasta_t* h, double dt_fm, int reps);
 
 /* Capture the steady-state step cycle (6 steps) in a HIP graph and replay it

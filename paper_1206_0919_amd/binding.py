@@ -51,6 +51,7 @@ _SIGS = {
     "shasta_set_persistent": ([_h, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "shasta_get_tiles": ([_h, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "shasta_get_persistent": ([_h, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "shasta_autotune": ([_h, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "shasta_set_graph": ([_h, ctypes.c_int], ctypes.c_int),
     "shasta_set_profiling": ([_h, ctypes.c_int], ctypes.c_int),
@@ -190,6 +191,20 @@ class Shasta:
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(self.h, shasta_get_tiles(self.h, axis, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def get_persistent(self, axis):
+        e = ctypes.c_int()
+        _check(self.h, shasta_get_persistent(self.h, axis, ctypes.byref(e)))
+        return bool(e.value)
+
+    def decomposition(self):
+        """Per axis (p0, p1, persistent): what shasta_autotune chose."""
+        return [(*self.get_tiles(a), int(self.get_persistent(a))) for a in range(3)]
+
+    def set_decomposition(self, dec):
+        for a, (p0, p1, pers) in enumerate(dec):
+            self.set_tiles(a, p0, p1)
+            self.set_persistent(a, pers)
 
     def autotune(self, dt, reps=3):
         _check(self.h, shasta_autotune(self.h, float(dt), int(reps)))

@@ -48,7 +48,13 @@ struct EventDesc {
   int32_t rec_count[3];
   int32_t xwin_begin;    // first x-sweep window of this event
   int32_t xwin_count;
+  int32_t fin_begin;     // first partial of the step reduction of this event
+  int32_t fin_count;     // its partials (records of the three sweeps / kFinChunk)
 };
+
+// Step reduction: one block reduces kFinChunk records to one partial of
+// R_SIZE doubles (the 13 record entries, then the non-finite probe).
+constexpr int kFinChunk = 256;
 
 // Work of one wave.
 struct Item {

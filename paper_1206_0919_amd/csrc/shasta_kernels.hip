@@ -78,6 +78,16 @@ __device__ __forceinline__ int item_at(const SweepArgs& A, int k) {
   return A.order ? A.order[k] : k;
 }
 
+// Block b of a launch runs on XCD b % 8.  Give each XCD a contiguous run of
+// blocks, in dispatch order, so that neighbouring work items (which share
+// cache lines of misaligned rows and the halo planes of adjacent segments)
+// meet in the same L2.  Bijective on [0, gridDim.x).
+__device__ __forceinline__ int xcd_block() {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int q = G >> 3, r = G & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // ------------------------------------------------------------ march (y, z)
 // Buffer descriptor of one field array (raw addressing, range checked by the
 // hardware: loads beyond num_records return 0, stores beyond are dropped).
@@ -329,7 +339,7 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
   __shared__ double part[16];
   __shared__ int next;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int k = blockIdx.x; k < A.n_items;) {
+  for (int k = PERSIST ? (int)blockIdx.x : xcd_block(); k < A.n_items;) {
   // wave-uniform: keeps the work item and the buffer descriptors scalar
   const int item = __builtin_amdgcn_readfirstlane(item_at(A, k));
   const Item it = A.items[item];
@@ -517,7 +527,8 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ T halo[kWavesPerBlock][3][kXWindow];
   // wave-uniform: lets the compiler keep the work item in scalar registers
-  for (int kq = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave);
+  for (int kq = __builtin_amdgcn_readfirstlane(
+           (PERSIST ? (int)blockIdx.x : xcd_block()) * kWavesPerBlock + wave);
        kq < A.n_items;) {
   const int item = __builtin_amdgcn_readfirstlane(item_at(A, kq));
   const Item it = A.items[item];
@@ -702,63 +713,105 @@ struct FinalizeArgs {
   double* acc;     // A_SIZE doubles per event
   double dt;
   int* counters;   // queue counters of the three sweeps, reset for the next step
+  double* partial; // R_SIZE doubles per partial
+  int* ticket;     // one per event, zero between steps
 };
 
-__global__ __launch_bounds__(256) void finalize_step(FinalizeArgs F) {
-  const EventDesc& ev = F.ev[blockIdx.x];
-  __shared__ double red[256][13];
-  if (blockIdx.x == 0 && threadIdx.x < 3) F.counters[threadIdx.x] = 0;
-  double v[13];
+// Adds one record to the thread's partials.  The 13 entries are those of a
+// sweep record; entry 13 collects x * 0 over the sums of every sweep, which
+// stays 0 unless one of them is infinite or NaN.  Sums count only for the
+// step's last sweep (the state at the end of the step).
+__device__ __forceinline__ void fin_add(const double* r, bool last, double (&v)[14]) {
 #pragma unroll
-  for (int j = 0; j < 13; ++j) v[j] = 0.0;
-  double sums3[3][5];
-#pragma unroll
-  for (int s = 0; s < 3; ++s)
-#pragma unroll
-    for (int q = 0; q < 5; ++q) sums3[s][q] = 0.0;
-  for (int s = 0; s < 3; ++s) {
-    const int ax = F.axis[s];
-    const double* r = F.rec[s] + (size_t)ev.rec_begin[ax] * R_SIZE;
-    for (int b = threadIdx.x; b < ev.rec_count[ax]; b += blockDim.x) {
-      const double* rb = r + (size_t)b * R_SIZE;
-      for (int q = 0; q < 5; ++q) {
-        sums3[s][q] += rb[R_SUM + q];
-        v[R_LEDGER + q] += rb[R_LEDGER + q];
-      }
-      v[R_MAXEPS] = fmax(v[R_MAXEPS], rb[R_MAXEPS]);
-      v[R_CLAMP] += rb[R_CLAMP];
-      v[R_FLOOR] += rb[R_FLOOR];
-    }
+  for (int q = 0; q < 5; ++q) {
+    if (last) v[R_SUM + q] += r[R_SUM + q];
+    v[13] += r[R_SUM + q] * 0.0;
+    v[R_LEDGER + q] += r[R_LEDGER + q];
   }
-  // sums of the last sweep; a non-finite sum of any sweep flags the step
-  bool bad = false;
-  for (int s = 0; s < 3; ++s)
-    for (int q = 0; q < 5; ++q) bad = bad || !isfinite(sums3[s][q]);
-  for (int q = 0; q < 5; ++q) v[R_SUM + q] = sums3[2][q];
-  for (int j = 0; j < 13; ++j) red[threadIdx.x][j] = v[j];
-  __shared__ int any_bad;
-  if (threadIdx.x == 0) any_bad = 0;
+  v[R_MAXEPS] = fmax(v[R_MAXEPS], r[R_MAXEPS]);
+  v[R_CLAMP] += r[R_CLAMP];
+  v[R_FLOOR] += r[R_FLOOR];
+}
+
+// Fixed-order reduction of the block's 256 thread partials (butterfly per
+// wave, then the four waves in order); the result is valid in thread 0.
+__device__ __forceinline__ void fin_block(double (&v)[14], double (*part)[14]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 14; ++j) v[j] = (j == R_MAXEPS) ? wave_max(v[j]) : wave_sum(v[j]);
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 14; ++j) part[wave][j] = v[j];
   __syncthreads();
-  if (bad) atomicOr(&any_bad, 1);
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int j = 0; j < 13; ++j)
-        red[threadIdx.x][j] = (j == R_MAXEPS)
-                                  ? fmax(red[threadIdx.x][j], red[threadIdx.x + w][j])
-                                  : red[threadIdx.x][j] + red[threadIdx.x + w][j];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double* a = F.acc + (size_t)blockIdx.x * A_SIZE;
-    for (int q = 0; q < 5; ++q) {
-      a[A_SUM + q] = red[0][R_SUM + q];
-      a[A_LEDGER + q] += red[0][R_LEDGER + q];
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kFinChunk / 64; ++w)
+#pragma unroll
+      for (int j = 0; j < 14; ++j)
+        v[j] = (j == R_MAXEPS) ? fmax(v[j], part[w][j]) : v[j] + part[w][j];
+}
+
+// Step reduction.  Block (c, e) reduces records [c * 256, c * 256 + 256) of
+// event e (the records of the step's three sweeps, in sweep order) to
+// partial c; the block that finishes last, found by a ticket per event,
+// combines the partials in index order and updates the event's accumulators.
+// The combination order is fixed, so the result does not depend on timing.
+// The last block leaves the ticket at zero for the next step.
+__global__ __launch_bounds__(kFinChunk) void finalize_step(FinalizeArgs F) {
+  const EventDesc& ev = F.ev[blockIdx.y];
+  const int c = blockIdx.x;
+  __shared__ double part[kFinChunk / 64][14];
+  __shared__ int is_last;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 3) F.counters[threadIdx.x] = 0;
+  if (c >= ev.fin_count) return;
+  double v[14];
+#pragma unroll
+  for (int j = 0; j < 14; ++j) v[j] = 0.0;
+  {
+    int i = c * kFinChunk + threadIdx.x;
+    for (int s = 0; s < 3; ++s) {
+      const int n = ev.rec_count[F.axis[s]];
+      if (i >= 0 && i < n)
+        fin_add(F.rec[s] + (size_t)(ev.rec_begin[F.axis[s]] + i) * R_SIZE, s == 2, v);
+      i -= n;
     }
-    a[A_MAXEPS] = fmax(a[A_MAXEPS], red[0][R_MAXEPS]);
+  }
+  fin_block(v, part);
+  double* mine = F.partial + (size_t)(ev.fin_begin + c) * R_SIZE;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 14; ++j) mine[j] = v[j];
+    __threadfence();
+    is_last = atomicAdd(F.ticket + blockIdx.y, 1) == ev.fin_count - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+#pragma unroll
+  for (int j = 0; j < 14; ++j) v[j] = 0.0;
+  for (int k = threadIdx.x; k < ev.fin_count; k += kFinChunk) {
+    const double* p = F.partial + (size_t)(ev.fin_begin + k) * R_SIZE;
+    double r[14];
+#pragma unroll
+    for (int j = 0; j < 14; ++j) r[j] = __builtin_nontemporal_load(p + j);
+#pragma unroll
+    for (int j = 0; j < 14; ++j) v[j] = (j == R_MAXEPS) ? fmax(v[j], r[j]) : v[j] + r[j];
+  }
+  __syncthreads();  // part[] is reused
+  fin_block(v, part);
+  if (threadIdx.x == 0) {
+    F.ticket[blockIdx.y] = 0;
+    bool bad = !(v[13] == 0.0);
+    for (int q = 0; q < 5; ++q) bad = bad || !isfinite(v[R_SUM + q]);
+    double* a = F.acc + (size_t)blockIdx.y * A_SIZE;
+    for (int q = 0; q < 5; ++q) {
+      a[A_SUM + q] = v[R_SUM + q];
+      a[A_LEDGER + q] += v[R_LEDGER + q];
+    }
+    a[A_MAXEPS] = fmax(a[A_MAXEPS], v[R_MAXEPS]);
     a[A_T] += F.dt;
-    a[A_CLAMP] += red[0][R_CLAMP];
-    a[A_FLOOR] += red[0][R_FLOOR];
-    a[A_NONFINITE] += any_bad ? 1.0 : 0.0;
+    a[A_CLAMP] += v[R_CLAMP];
+    a[A_FLOOR] += v[R_FLOOR];
+    a[A_NONFINITE] += bad ? 1.0 : 0.0;
     a[A_STEPS] += 1.0;
   }
 }
@@ -946,16 +999,18 @@ int resident(int fp32, int eos_kind, int axis) {
   return fp32 ? resident_blocks<float, 1>(axis) : resident_blocks<double, 1>(axis);
 }
 
-hipError_t finalize(const EventDesc* ev, int n_events, const double* const rec[3],
-                    const int axis[3], double* acc, double dt, int* counters,
-                    hipStream_t st) {
+hipError_t finalize(const EventDesc* ev, int n_events, int max_chunks,
+                    const double* const rec[3], const int axis[3], double* acc, double dt,
+                    int* counters, double* partial, int* ticket, hipStream_t st) {
   FinalizeArgs f;
   f.counters = counters;
+  f.partial = partial;
+  f.ticket = ticket;
   f.ev = ev;
   for (int s = 0; s < 3; ++s) { f.rec[s] = rec[s]; f.axis[s] = axis[s]; }
   f.acc = acc;
   f.dt = dt;
-  hipLaunchKernelGGL(finalize_step, dim3(n_events), dim3(256), 0, st, f);
+  hipLaunchKernelGGL(finalize_step, dim3(max_chunks, n_events), dim3(kFinChunk), 0, st, f);
   return hipGetLastError();
 }
 

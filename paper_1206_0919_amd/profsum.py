@@ -7,6 +7,7 @@ Prints a markdown table: per kernel, calls, average duration, and for
 counter runs the average counter value per dispatch.
 """
 import csv
+import re
 import glob
 import os
 import sys
@@ -18,12 +19,17 @@ def _find(d, pattern):
 
 
 def short(name):
-    """Readable kernel name: sweep_x / sweep_y / sweep_z plus template flags."""
-    if "sweep_march" in name:
-        axis = "y" if "Li1E" in name.split("sweep_march", 1)[1][:12] else "z"
-        return f"sweep_{axis}" + ("<f32>" if "IfLi" in name else "<f64>")
-    if "sweep_x" in name:
-        return "sweep_x" + ("<f32>" if "sweep_xIf" in name else "<f64>")
+    """Readable kernel name: sweep_x / sweep_y / sweep_z plus the precision.
+    Accepts demangled ("void shasta::sweep_march<double, 1, 0, false>(...)")
+    and mangled ("_ZN6shasta11sweep_marchIdLi1ELi0ELb0EE...") names."""
+    m = re.search(r"sweep_march<(\w+), (\d)", name) or \
+        re.search(r"sweep_marchI([df])Li(\d)E", name)
+    if m:
+        prec = "f32" if m.group(1) in ("float", "f") else "f64"
+        return f"sweep_{'xyz'[int(m.group(2))]}<{prec}>"
+    m = re.search(r"sweep_x<(\w+)", name) or re.search(r"sweep_xI([df])", name)
+    if m:
+        return "sweep_x<" + ("f32" if m.group(1) in ("float", "f") else "f64") + ">"
     for key in ("finalize_step", "stream_copy", "prim_to_cons", "read_out", "sum_fields",
                 "combine_sums", "zero_doubles", "cons_in"):
         if key in name:
