@@ -70,8 +70,11 @@ typedef struct shasta_handle shasta_t;
 
 /*
  * Create a handle for a batch of n_events independent grids (a single grid
- * is a batch of 1).  dims[3*k+0..2] = nx, ny, nz of event k, each >= 1, at
- * most 2^31-1 cells per event; dx_fm > 0 is the cell size of every event;
+ * is a batch of 1).  dims[3*k+0..2] = nx, ny, nz of event k, each >= 1;
+ * one field array of an event must stay below 2^31 bytes (the kernels
+ * address fields with 32-bit byte offsets): at most 268,434,943 cells per
+ * event in FP64, 536,869,887 in FP32; dx_fm > 0 is the cell size of every
+ * event;
  * precision is SHASTA_FP64 or SHASTA_FP32_MIXED; bc must be
  * SHASTA_BC_OUTFLOW; hip_stream is a hipStream_t (NULL = default stream).
  * Validation is done on the CPU before any HIP call; nothing is allocated on

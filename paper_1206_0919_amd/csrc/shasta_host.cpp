@@ -563,7 +563,9 @@ int shasta_create(shasta_t** out, int n_events, const int32_t* dims, double dx_f
       if (dims[3 * e + a] < 1) return SHASTA_EINVAL;
       c *= dims[3 * e + a];
     }
-    if (c > 2147483647LL - 4096) return SHASTA_EINVAL;
+    // one field array below 2^31 bytes: 32-bit buffer offsets and ranges
+    const int64_t elem = precision == SHASTA_FP32_MIXED ? 4 : 8;
+    if (c > (2147483647LL - 4096) / elem) return SHASTA_EINVAL;
   }
   shasta_t* h = new (std::nothrow) shasta_t();
   if (!h) return SHASTA_EINVAL;

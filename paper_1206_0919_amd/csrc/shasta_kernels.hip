@@ -101,6 +101,11 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off) {
   else
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
+// Byte offset that lies beyond every field array (each is below 2^31 bytes):
+// a buffer store there is discarded by the range check, which masks stores
+// lane by lane without a branch.
+constexpr int kDropOffset = (int)0x80000000u;
+
 template <typename T>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v) {
   if constexpr (sizeof(T) == 8)
@@ -115,9 +120,13 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 //   producer P: loads U^n, recovery at U^n, lambda/2 predictor -> U^{n+1/2};
 //   consumer C: recovery at U^{n+1/2}, lambda corrector from U^n -> U^{n+1},
 //               stores, reductions.
-// P hands U^n (ring of 8 rows) and U^{n+1/2} (ring of 2 rows) to C through
-// LDS; one barrier per iteration keeps C one iteration behind P.  Each wave
-// carries about half of the pipeline state, so two pairs fit on a SIMD.
+// P hands U^n (ring of 8 rows) and U^{n+1/2} (ring of 4 rows) to C through
+// LDS.  The pair meets at a barrier every kSync = 2 iterations and C runs
+// kSync iterations behind P: at trip t P writes U^n slot t & 7 and U^{n+1/2}
+// slot t & 3 while C reads U^n slot (t - 5) & 7 and U^{n+1/2} slot
+// (t - 2) & 3, all written before the previous barrier and not rewritten
+// before the next one.  Each wave carries about half of the pipeline state,
+// so two pairs fit on a SIMD.
 //
 // Every windowed quantity lives in a ring of 8 slots: the value of cell p is
 // in slot (p - i_lo) & 7.  The loop body is instantiated for the 8 phases, so
@@ -126,10 +135,15 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 // hat Delta of i-2, antiflux and U^{n+1/2} of cell i-3.  At C's iteration i
 // (one loop trip later): recovery of U^{n+1/2} at i-3, hat U of cell i-4,
 // hat Delta of i-5, antiflux and U^{n+1} of cell i-6.
+constexpr int kSync = 2;   // trips between the barriers of a P/C pair
+// The loop bodies below place a barrier after odd phases and index the
+// U^{n+1/2} ring with & 3; the U^n ring needs 2 kSync + 3 < 8.
+static_assert(kSync == 2, "barrier placement and ring sizes assume kSync = 2");
+
 template <typename T>
 struct RingLds {
-  T un[8][kNF][64];   // U^n rows, slot (p - i_lo) & 7
-  T uh[2][kNF][64];   // U^{n+1/2} rows, slot = loop trip & 1
+  T un[8][kNF][64];          // U^n rows, slot (p - i_lo) & 7
+  T uh[2 * kSync][kNF][64];  // U^{n+1/2} rows, slot = loop trip & 3
 };
 
 template <typename T, int AXIS, int EOS>
@@ -351,16 +365,16 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
     const int64_t fbytes = ev.ncell * (int64_t)sizeof(T);
     const T* base = reinterpret_cast<const T*>(A.field_base);
     const int i_lo = it.s0 - kMarchLag;
-    const int trips = it.s1 - it.s0 + 2 * kMarchLag + 1;   // C runs one trip behind
+    const int trips = it.s1 - it.s0 + 2 * kMarchLag + kSync;   // C runs kSync trips behind
     const int N = ev.n[AXIS];
     // A chunk of 8 trips is "interior" when no trip of either wave meets a
     // pencil end, a halo rule or a cell outside the written segment.
-    // P at trip t handles cell i = i_lo + t; C handles k = i_lo + t - 4 and
-    // o = i_lo + t - 7.
+    // P at trip t handles cell i = i_lo + t; C handles k = i_lo + t - 2 - 3
+    // and o = i_lo + t - 2 - 6.
     auto interior = [&](int j) {
       const int iP0 = i_lo + j, iP1 = i_lo + j + 7;
-      const int k0 = i_lo + j - 4, k1 = i_lo + j + 3;
-      const int o0 = i_lo + j - 7, o1 = i_lo + j;
+      const int k0 = i_lo + j - kSync - 3, k1 = k0 + 7;
+      const int o0 = i_lo + j - kSync - kMarchLag, o1 = o0 + 7;
       return j >= 1 && iP0 >= it.s0 && iP1 < it.s1 && k0 >= 1 &&
              k1 <= N - 2 && k0 >= it.s0 && k1 < it.s1 && o0 >= it.s0 && o1 < it.s1;
     };
@@ -375,7 +389,10 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
       P.template load<0>(i_lo);
       if constexpr (kPrefetch >= 2) P.template load<1>(i_lo + 1);
       if constexpr (kPrefetch >= 3) P.template load<2>(i_lo + 2);
-#define SHASTA_P(PH, E) P.template iterate<PH, E>(i + PH, L, PH & 1); __syncthreads();
+#define SHASTA_P(PH, E)                                                  \
+  P.template iterate<PH, E>(i + PH, L, PH & 3);                          \
+  if constexpr ((PH & 1) == 1) __syncthreads();                          \
+  else asm volatile("" ::: "memory");
 #define SHASTA_P8(E)                                                           \
   {                                                                            \
     const int i = i_lo + j;                                                    \
@@ -398,14 +415,17 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
       for (int q = 0; q < kNF; ++q)
         Cw.dst[q] = field_rsrc(base + ev.off[A.parity ^ 1] + q * ev.pitch, fbytes);
       Cw.init();
-      // C at trip j handles P's iteration of trip j-1 (virtual cell i-1)
+      // C at trip t handles P's iteration of trip t - 2 (cell i_lo + t - 2).
+      // Its first kSync trips read ring slots P has not written yet: they
+      // produce values only for cells more than 5 cells before the segment,
+      // which reach no stored cell, no counter and no ledger entry.
 #define SHASTA_C(PH, E)                                                            \
-  if (E == false || j + PH > 0)                                                    \
-    Cw.template iterate<(PH + 7) & 7, E>(i + PH, L, (PH + 1) & 1);                 \
-  __syncthreads();
+  Cw.template iterate<(PH + 8 - kSync) & 7, E>(i + PH, L, (PH + 4 - kSync) & 3);   \
+  if constexpr ((PH & 1) == 1) __syncthreads();                                    \
+  else asm volatile("" ::: "memory");
 #define SHASTA_C8(E)                                                               \
   {                                                                                \
-    const int i = i_lo + j - 1;                                                    \
+    const int i = i_lo + j - kSync;                                                \
     SHASTA_C(0, E) SHASTA_C(1, E) SHASTA_C(2, E) SHASTA_C(3, E)                    \
     SHASTA_C(4, E) SHASTA_C(5, E) SHASTA_C(6, E) SHASTA_C(7, E)                    \
   }
@@ -522,7 +542,8 @@ __device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCel
 }
 
 template <typename T, int EOS, bool PERSIST>
-__global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
+__global__ __launch_bounds__(256)
+void sweep_x(SweepArgs A) {
   constexpr int QP = 1, QT1 = 2, QT2 = 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ T halo[kWavesPerBlock][3][kXWindow];
@@ -535,12 +556,18 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
   double acc[13];
 #pragma unroll
   for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+  int n_clamp = 0, n_floor = 0;
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
     const int nx = ev.n[0];
     const T* src = reinterpret_cast<const T*>(A.field_base) + ev.off[A.parity];
-    T* dst = reinterpret_cast<T*>(A.field_base) + ev.off[A.parity ^ 1];
     const int64_t pitch = ev.pitch;
+    __amdgpu_buffer_rsrc_t dst[kNF];
+#pragma unroll
+    for (int q = 0; q < kNF; ++q)
+      dst[q] = field_rsrc(reinterpret_cast<const T*>(A.field_base) + ev.off[A.parity ^ 1] +
+                              q * pitch,
+                          ev.ncell * (int64_t)sizeof(T));
     const int2* win = A.xwin + ev.xwin_begin;
     const double lam = A.lam;
     const double lamh = 0.5 * lam;
@@ -598,10 +625,8 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
         ep[j] = T(lamh * v);
         fE[j] = T(r.p * v);
         fM[j] = T(r.p);
-        if (out_ok[j]) {
-          acc[R_CLAMP] += r.clamped;
-          acc[R_FLOOR] += r.floored;
-        }
+        n_clamp += out_ok[j] & (r.clamped != 0);
+        n_floor += out_ok[j] & (r.floored != 0);
       }
       // ---- U^n neighbours p-1, p+1, p+2 (kept for both half steps)
       T b_l[kNF], b_r0[kNF], b_r1[kNF];
@@ -639,27 +664,27 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
         ec[j] = T(lam * v);
         fEc[j] = T(r.p * v);
         fMc[j] = T(r.p);
-        if (out_ok[j]) {
-          acc[R_CLAMP] += r.clamped;
-          acc[R_FLOOR] += r.floored;
-          acc[R_MAXEPS] = fmax(acc[R_MAXEPS], fabs(double(ec[j])));
-        }
-        hE[kXCells * lane + j] = ec[j];
-        hF[kXCells * lane + j] = fEc[j];
-        hG[kXCells * lane + j] = fMc[j];
+        n_clamp += out_ok[j] & (r.clamped != 0);
+        n_floor += out_ok[j] & (r.floored != 0);
+        acc[R_MAXEPS] = out_ok[j] ? fmax(acc[R_MAXEPS], fabs(double(ec[j]))) : acc[R_MAXEPS];
+        // table entry of position p at (p % kXCells) * 64 + p / kXCells:
+        // a wave's writes and own-position reads touch distinct banks
+        hE[j * 64 + lane] = ec[j];
+        hF[j * 64 + lane] = fEc[j];
+        hG[j * 64 + lane] = fMc[j];
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
+        // a halo position reads its edge cell's entry, every other one its own
         const bool ghost = used[j] && (xs[j] < 0 || xs[j] >= nx);
-        if (ghost) {
-          const int pe = kXCells * lane + j + (min(max(xs[j], 0), nx - 1) - xs[j]);
-          ec[j] = hE[pe];
-          fEc[j] = hF[pe];
-          fMc[j] = hG[pe];
-        }
+        const int pe = kXCells * lane + j + (ghost ? min(max(xs[j], 0), nx - 1) - xs[j] : 0);
+        const int te = (pe % kXCells) * 64 + pe / kXCells;
+        ec[j] = hE[te];
+        fEc[j] = hF[te];
+        fMc[j] = hG[te];
       }
       // the table is rewritten by the next window
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -680,21 +705,28 @@ __global__ __launch_bounds__(256) void sweep_x(SweepArgs A) {
         x_fct(u[q], ul, ur, ur2, k, s, diff8, out);
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) {
-          if (out_ok[j]) {
-            dst[q * pitch + cell[j]] = out[j];
-            acc[R_SUM + q] += double(out[j]);
-            const bool first = xs[j] == 0, last = xs[j] == nx - 1;
-            if (first || last) {
-              const double f = (q == 0) ? double(fEc[j]) : ((q == QP) ? double(fMc[j]) : 0.0);
-              const double F = face_flux(double(ec[j]), double(u[q][j]), lam, f);
-              if (last) acc[R_LEDGER + q] += F;
-              if (first) acc[R_LEDGER + q] -= F;
-            }
+          buf_store<T>(dst[q], out_ok[j] ? cell[j] * (int)sizeof(T) : kDropOffset, out[j]);
+          acc[R_SUM + q] += out_ok[j] ? double(out[j]) : 0.0;
+        }
+      }
+      // boundary ledger: flux through the outflow faces (corrector)
+#pragma unroll
+      for (int j = 0; j < kXCells; ++j) {
+        const bool first = out_ok[j] && xs[j] == 0, last = out_ok[j] && xs[j] == nx - 1;
+        if (any_lane(first || last)) {
+#pragma unroll
+          for (int q = 0; q < kNF; ++q) {
+            const double f = (q == 0) ? double(fEc[j]) : ((q == QP) ? double(fMc[j]) : 0.0);
+            const double F = face_flux(double(ec[j]), double(u[q][j]), lam, f);
+            acc[R_LEDGER + q] = last ? acc[R_LEDGER + q] + F : acc[R_LEDGER + q];
+            acc[R_LEDGER + q] = first ? acc[R_LEDGER + q] - F : acc[R_LEDGER + q];
           }
         }
       }
     }
   }
+  acc[R_CLAMP] = double(n_clamp);
+  acc[R_FLOOR] = double(n_floor);
   wave_record(acc, A.rec, item);
   if (!PERSIST) break;
   int nk = 0;

@@ -113,13 +113,10 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
   r.clamped = M2 > kE2;
   const double M2c = r.clamped ? kE2 : M2;
   double w, e;
+  bool rare;
   if constexpr (EOS == 0) {
-    const bool rare = !(Ec > 1e-140 && Ec < 1e140);
+    rare = !(Ec > 1e-140 && Ec < 1e140);
     ideal_root(Ec, M2c, w, e);
-    if (any_lane(rare)) {
-      if (rare) ideal_root_scaled(Ec, M2c, w, e);
-    }
-    r.p = e * kThird;
   } else {
     // bag model: the recovery function v (E + p(E - M v)) - M increases with
     // v, so its sign at the edges of the mixed phase selects the branch:
@@ -138,16 +135,18 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
     w = rcp(den);
     e = __builtin_fma(-M2c, w, Ec);
     r.p = mixed ? pc : __builtin_fma(kThird, e, b);
-    const bool rare = hadron && !(Ec > 1e-140);
-    if (any_lane(rare)) {
-      if (rare) {
-        ideal_root_scaled(Ec, M2c, w, e);
-        r.p = e * kThird;
-      }
-    }
+    rare = hadron && !(Ec > 1e-140);
   }
-  // v_i = v M_i / |M| = w M_c M_i / |M|; M_c = |M| unless clamped
-  if (any_lane(r.clamped)) {
+  if constexpr (EOS == 0) r.p = e * kThird;
+  // One wave-uniform branch for both rare paths: scaled root (the squares
+  // would leave the normal range; on the bag EOS only in the hadron phase)
+  // and clamped |M|: v_i = v M_i / |M| = w M_c M_i / |M|, M_c = |M| unless
+  // clamped.
+  if (any_lane(rare || r.clamped)) {
+    if (rare) {
+      ideal_root_scaled(Ec, M2c, w, e);
+      r.p = e * kThird;
+    }
     if (r.clamped) w *= kE * rcp(sqrt_pos(M2));
   }
   r.w = w;

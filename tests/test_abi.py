@@ -55,6 +55,9 @@ def test_create_validation(b):
     assert _create(b, 1, [4, 4, 4], prec=2)[0] == b.EINVAL
     assert _create(b, 1, [4, 4, 4], bc=1)[0] == b.EINVAL
     assert _create(b, 1, [2048, 2048, 1024])[0] == b.EINVAL  # > 2^31 cells
+    # one field array must stay below 2^31 bytes (32-bit buffer offsets)
+    assert _create(b, 1, [1024, 1024, 257])[0] == b.EINVAL            # FP64: 2.06 GiB
+    assert _create(b, 1, [1024, 1024, 513], prec=1)[0] == b.EINVAL    # FP32: 2.004 GiB
     st, h = _create(b, 2, [4, 5, 6, 48, 64, 96], prec=1)
     assert st == b.OK
     nb = ctypes.c_size_t()
