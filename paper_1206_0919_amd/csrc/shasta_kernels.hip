@@ -27,12 +27,7 @@
 
 namespace shasta {
 
-// Rows the producer wave of the march loads ahead of use.
-#ifndef SHASTA_MARCH_PREFETCH
-#define SHASTA_MARCH_PREFETCH 2
-#endif
-constexpr int kPrefetch = SHASTA_MARCH_PREFETCH;
-static_assert(kPrefetch >= 1 && kPrefetch <= 3, "ring of 8 slots: lifetime 4 + prefetch < 8");
+
 
 struct SweepArgs {
   const EventDesc* ev;
@@ -120,13 +115,12 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 //   producer P: loads U^n, recovery at U^n, lambda/2 predictor -> U^{n+1/2};
 //   consumer C: recovery at U^{n+1/2}, lambda corrector from U^n -> U^{n+1},
 //               stores, reductions.
-// P hands U^n (ring of 8 rows) and U^{n+1/2} (ring of 4 rows) to C through
-// LDS.  The pair meets at a barrier every kSync = 2 iterations and C runs
-// kSync iterations behind P: at trip t P writes U^n slot t & 7 and U^{n+1/2}
-// slot t & 3 while C reads U^n slot (t - 5) & 7 and U^{n+1/2} slot
-// (t - 2) & 3, all written before the previous barrier and not rewritten
-// before the next one.  Each wave carries about half of the pipeline state,
-// so two pairs fit on a SIMD.
+// P hands U^n and U^{n+1/2} to C through LDS rings.  The pair meets at a
+// barrier every S iterations and C runs S iterations behind P: at trip t P
+// writes U^n slot t mod (2S + 3) and U^{n+1/2} slot t mod 2S while C reads
+// U^n slot (t - S - 3) mod (2S + 3) and U^{n+1/2} slot (t - S) mod 2S, all
+// written before the previous barrier and not rewritten before the next one.
+// Each wave carries about half of the pipeline state.
 //
 // Every windowed quantity lives in a ring of 8 slots: the value of cell p is
 // in slot (p - i_lo) & 7.  The loop body is instantiated for the 8 phases, so
@@ -135,15 +129,31 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 // hat Delta of i-2, antiflux and U^{n+1/2} of cell i-3.  At C's iteration i
 // (one loop trip later): recovery of U^{n+1/2} at i-3, hat U of cell i-4,
 // hat Delta of i-5, antiflux and U^{n+1} of cell i-6.
-constexpr int kSync = 2;   // trips between the barriers of a P/C pair
-// The loop bodies below place a barrier after odd phases and index the
-// U^{n+1/2} ring with & 3; the U^n ring needs 2 kSync + 3 < 8.
-static_assert(kSync == 2, "barrier placement and ring sizes assume kSync = 2");
+// Configuration of the march per precision and EOS.  FP64 on the ideal gas
+// runs three pairs per SIMD: 168 registers and 23 KB of LDS per pair, which
+// needs a barrier every trip (S = 1) and one row of prefetch.  The others
+// keep S = 2 and two rows of prefetch: FP32 fits three pairs anyway, FP64 on
+// the bag EOS needs more registers than three pairs allow.
+template <typename T, int EOS>
+struct MarchCfg {
+  static constexpr bool tight = sizeof(T) == 8 && EOS == 0;
+  static constexpr int sync = tight ? 1 : 2;        // trips between barriers
+  static constexpr int prefetch = tight ? 1 : 2;    // rows P loads ahead
+  static constexpr int waves = (sizeof(T) == 8 && EOS == 1) ? 2 : 3;  // per SIMD
+  static constexpr int un_slots = 2 * sync + 3;     // U^n rows between P and C
+  static_assert(sync == 1 || sync == 2, "the 8-phase loop body needs S in {1, 2}");
+  static_assert(prefetch >= 1 && prefetch <= 3, "register ring of 8: lifetime 4 + prefetch");
+};
 
-template <typename T>
+template <typename T, int S>
 struct RingLds {
-  T un[8][kNF][64];          // U^n rows, slot (p - i_lo) & 7
-  T uh[2 * kSync][kNF][64];  // U^{n+1/2} rows, slot = loop trip & 3
+  T un[2 * S + 3][kNF][64];  // U^n rows, slot = loop trip mod (2S + 3)
+  T uh[2 * S][kNF][64];      // U^{n+1/2} rows, slot = loop trip mod 2S
+  // C's per-lane FP64 accumulators of the written cells' sums and of the
+  // boundary ledger: kept in LDS, not in registers, through the whole march
+  // (each lane adds only to its own entries, in program order).
+  double sum[kNF][64];
+  double ledger[kNF][64];
 };
 
 template <typename T, int AXIS, int EOS>
@@ -156,7 +166,8 @@ struct MarchCommon {
   const EosParams* eos;
   double lam, lamh;
   T lamsrc, diff8;
-  double acc[13];
+  int n_clamp, n_floor;   // recoveries guarded, cells of the segment only
+  double maxeps;          // C only
 };
 
 template <typename T, int AXIS, int EOS>
@@ -183,14 +194,15 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
     for (int q = 0; q < kNF; ++q) u[q][PH & 7] = buf_load<T>(src[q], o);
   }
   // EDGE = false: the caller guarantees that cell i is inside [s0, s1).
-  template <int PH, bool EDGE>
-  __device__ __forceinline__ void iterate(int i, RingLds<T>& L, int hslot) {
+  template <int PH, bool EDGE, class Ring>
+  __device__ __forceinline__ void iterate(int i, Ring& L, int hslot, int uslot) {
     constexpr int S0 = PH & 7, S1 = (PH - 1) & 7, S2 = (PH - 2) & 7, S3 = (PH - 3) & 7,
                   S4 = (PH - 4) & 7;
     constexpr int QP = C::QP, QT1 = C::QT1, QT2 = C::QT2;
-    load<PH + kPrefetch>(i + kPrefetch);  // prefetch
+    constexpr int PF = MarchCfg<T, EOS>::prefetch;
+    load<PH + PF>(i + PF);  // prefetch
 #pragma unroll
-    for (int q = 0; q < kNF; ++q) L.un[S0][q][this->lane] = u[q][S0];
+    for (int q = 0; q < kNF; ++q) L.un[uslot][q][this->lane] = u[q][S0];
     {
       const Recovered r = recover<EOS>(*this->eos, double(u[0][S0]), double(u[QP][S0]),
                                        double(u[QT1][S0]), double(u[QT2][S0]));
@@ -199,8 +211,8 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
       fE[S0] = T(r.p * v);
       fM[S0] = T(r.p);
       if (this->active && (!EDGE || (i >= this->s0 && i < this->s1))) {
-        this->acc[R_CLAMP] += r.clamped;
-        this->acc[R_FLOOR] += r.floored;
+        this->n_clamp += r.clamped;
+        this->n_floor += r.floored;
       }
     }
     rd[S0] = interface_rcp(ep[S1], ep[S0]);
@@ -240,8 +252,8 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
   }
   // EDGE = false: the caller guarantees 1 <= k <= N-2, k and o inside
   // [s0, s1) (no pencil end, no halo rule, every result is stored).
-  template <int PH, bool EDGE>
-  __device__ __forceinline__ void iterate(int i, const RingLds<T>& L, int hslot) {
+  template <int PH, bool EDGE, class Ring>
+  __device__ __forceinline__ void iterate(int i, Ring& L, int hslot, int uslot) {
     constexpr int S3 = (PH - 3) & 7, S4 = (PH - 4) & 7, S5 = (PH - 5) & 7, S6 = (PH - 6) & 7,
                   S7 = (PH - 7) & 7;
     constexpr int QP = C::QP, QT1 = C::QT1, QT2 = C::QT2;
@@ -250,7 +262,7 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
     T uh[kNF];
 #pragma unroll
     for (int q = 0; q < kNF; ++q) {
-      u[q][S3] = L.un[S3][q][this->lane];
+      u[q][S3] = L.un[uslot][q][this->lane];
       uh[q] = L.uh[hslot][q][this->lane];
       d[q][S4] = u[q][S3] - u[q][S4];                                    // Delta_{i-4}
       q2[q][S5] = second_difference(d[q][S4], d[q][S6], d[q][S5]);      // at i-5
@@ -269,9 +281,9 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       fE[S3] = T(r.p * v);
       fM[S3] = T(r.p);
       if (this->active && (!EDGE || (k >= this->s0 && k < this->s1))) {
-        this->acc[R_CLAMP] += r.clamped;
-        this->acc[R_FLOOR] += r.floored;
-        this->acc[R_MAXEPS] = fmax(this->acc[R_MAXEPS], fabs(double(ec[S3])));
+        this->n_clamp += r.clamped;
+        this->n_floor += r.floored;
+        this->maxeps = fmax(this->maxeps, fabs(double(ec[S3])));
       }
     }
     const bool left_edge = EDGE && (k == 0);
@@ -288,8 +300,8 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       for (int q = 0; q < kNF; ++q) {
         const double f = (q == 0) ? double(fE[S3]) : ((q == QP) ? double(fM[S3]) : 0.0);
         const double F = face_flux(e64, double(u[q][S3]), this->lam, f);
-        if (left_edge) this->acc[R_LEDGER + q] -= F;
-        if (k == N - 1) this->acc[R_LEDGER + q] += F;
+        if (left_edge) L.ledger[q][this->lane] -= F;
+        if (k == N - 1) L.ledger[q][this->lane] += F;
       }
     }
     // ---- corrector of cell i-4 .. U^{n+1} of cell o = i-6
@@ -310,7 +322,8 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       const T out = update(hc[q][S6], ac[q][S6], ac[q][S7]);            // U^{n+1}_{i-6}
       if (store) {
         buf_store<T>(dst[q], ooff, out);
-        this->acc[R_SUM + q] += double(out);
+        __hip_atomic_fetch_add(&L.sum[q][this->lane], double(out), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
       }
     }
   }
@@ -340,16 +353,21 @@ __device__ __forceinline__ void march_setup(M& m, const SweepArgs& A, const Item
   m.diff8 = TT(A.diff * 0.125);
   m.s0 = it.s0;
   m.s1 = it.s1;
-#pragma unroll
-  for (int j = 0; j < 13; ++j) m.acc[j] = 0.0;
+  m.n_clamp = 0;
+  m.n_floor = 0;
+  m.maxeps = 0.0;
 }
 
 // AXIS = 1 (y) or 2 (z).  Block = one producer/consumer pair; it processes
 // one work item, or, in a persistent launch, items from the queue until the
 // queue is empty.
 template <typename T, int AXIS, int EOS, bool PERSIST>
-__global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
-  __shared__ RingLds<T> L;
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MarchCfg<T, EOS>::waves)))
+void sweep_march(SweepArgs A) {
+  constexpr int kSync = MarchCfg<T, EOS>::sync;
+  constexpr int kUnSlots = MarchCfg<T, EOS>::un_slots;
+  constexpr int kPrefetch = MarchCfg<T, EOS>::prefetch;
+  __shared__ RingLds<T, kSync> L;
   __shared__ double part[16];
   __shared__ int next;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -369,8 +387,8 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
     const int N = ev.n[AXIS];
     // A chunk of 8 trips is "interior" when no trip of either wave meets a
     // pencil end, a halo rule or a cell outside the written segment.
-    // P at trip t handles cell i = i_lo + t; C handles k = i_lo + t - 2 - 3
-    // and o = i_lo + t - 2 - 6.
+    // P at trip t handles cell i = i_lo + t; C handles k = i_lo + t - kSync - 3
+    // and o = i_lo + t - kSync - 6.
     auto interior = [&](int j) {
       const int iP0 = i_lo + j, iP1 = i_lo + j + 7;
       const int k0 = i_lo + j - kSync - 3, k1 = k0 + 7;
@@ -389,9 +407,9 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
       P.template load<0>(i_lo);
       if constexpr (kPrefetch >= 2) P.template load<1>(i_lo + 1);
       if constexpr (kPrefetch >= 3) P.template load<2>(i_lo + 2);
-#define SHASTA_P(PH, E)                                                  \
-  P.template iterate<PH, E>(i + PH, L, PH & 3);                          \
-  if constexpr ((PH & 1) == 1) __syncthreads();                          \
+#define SHASTA_P(PH, E)                                                        \
+  P.template iterate<PH, E>(i + PH, L, PH % (2 * kSync), (j + PH) % kUnSlots);  \
+  if constexpr (PH % kSync == kSync - 1) __syncthreads();                      \
   else asm volatile("" ::: "memory");
 #define SHASTA_P8(E)                                                           \
   {                                                                            \
@@ -405,8 +423,8 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
       for (; j < trips; j += 8) SHASTA_P8(true)
 #undef SHASTA_P8
 #undef SHASTA_P
-#pragma unroll
-      for (int j = 0; j < 13; ++j) acc[j] = P.acc[j];
+      acc[R_CLAMP] = P.active ? double(P.n_clamp) : 0.0;
+      acc[R_FLOOR] = P.active ? double(P.n_floor) : 0.0;
     } else {
       MarchC<T, AXIS, EOS> Cw;
       march_setup(Cw, A, it, ev, AXIS, lane);
@@ -415,13 +433,21 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
       for (int q = 0; q < kNF; ++q)
         Cw.dst[q] = field_rsrc(base + ev.off[A.parity ^ 1] + q * ev.pitch, fbytes);
       Cw.init();
-      // C at trip t handles P's iteration of trip t - 2 (cell i_lo + t - 2).
-      // Its first kSync trips read ring slots P has not written yet: they
-      // produce values only for cells more than 5 cells before the segment,
-      // which reach no stored cell, no counter and no ledger entry.
+#pragma unroll
+      for (int q = 0; q < kNF; ++q) {
+        L.sum[q][lane] = 0.0;
+        L.ledger[q][lane] = 0.0;
+      }
+      // C at trip t handles P's iteration of trip t - kSync (cell
+      // i_lo + t - kSync).  Its first kSync trips read ring slots P has not
+      // written yet: they produce values only for cells more than 5 cells
+      // before the segment, which reach no stored cell, no counter and no
+      // ledger entry.
 #define SHASTA_C(PH, E)                                                            \
-  Cw.template iterate<(PH + 8 - kSync) & 7, E>(i + PH, L, (PH + 4 - kSync) & 3);   \
-  if constexpr ((PH & 1) == 1) __syncthreads();                                    \
+  Cw.template iterate<(PH + 8 - kSync) & 7, E>(                                    \
+      i + PH, L, (PH + kSync) % (2 * kSync),                                       \
+      (j + PH + 2 * kUnSlots - kSync - 3) % kUnSlots);                             \
+  if constexpr (PH % kSync == kSync - 1) __syncthreads();                          \
   else asm volatile("" ::: "memory");
 #define SHASTA_C8(E)                                                               \
   {                                                                                \
@@ -435,8 +461,16 @@ __global__ __launch_bounds__(128) void sweep_march(SweepArgs A) {
       for (; j < trips; j += 8) SHASTA_C8(true)
 #undef SHASTA_C8
 #undef SHASTA_C
+      if (Cw.active) {
 #pragma unroll
-      for (int j = 0; j < 13; ++j) acc[j] = Cw.acc[j];
+        for (int q = 0; q < kNF; ++q) {
+          acc[R_SUM + q] = L.sum[q][lane];
+          acc[R_LEDGER + q] = L.ledger[q][lane];
+        }
+        acc[R_MAXEPS] = Cw.maxeps;
+        acc[R_CLAMP] = double(Cw.n_clamp);
+        acc[R_FLOOR] = double(Cw.n_floor);
+      }
     }
   }
   // one record per item: consumer and producer parts summed in a fixed order
@@ -578,42 +612,55 @@ void sweep_x(SweepArgs A) {
     T* hF = halo[wave][1];
     T* hG = halo[wave][2];
 
-    for (int w = it.a; w < it.a + it.b; ++w) {
-      const int2 cw = win[w];
-      const int c0 = cw.x, c1 = cw.y;
-      // ---- map the owned positions to (cell, x) by walking the row pieces
+    // ---- map the owned positions of window w to (cell, x) by walking its
+    //      row pieces
+    struct XMap {
       int cell[kXCells], xs[kXCells];
       bool used[kXCells], out_ok[kXCells];
+    };
+    auto map_window = [&](int w) {
+      const int2 cw = win[w];
+      const int c0 = cw.x, c1 = cw.y;
+      XMap m;
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        cell[j] = c0; xs[j] = 0; used[j] = false; out_ok[j] = false;
+        m.cell[j] = c0; m.xs[j] = 0; m.used[j] = false; m.out_ok[j] = false;
       }
-      {
-        int ps = 0, c = c0;
-        while (c < c1) {
-          const int row0 = c - (c % nx);            // first cell of the row
-          const int x0 = c - row0;
-          const int len = min(nx - x0, c1 - c);
+      int ps = 0, c = c0;
+      while (c < c1) {
+        const int row0 = c - (c % nx);            // first cell of the row
+        const int x0 = c - row0;
+        const int len = min(nx - x0, c1 - c);
 #pragma unroll
-          for (int j = 0; j < kXCells; ++j) {
-            const int r = kXCells * lane + j - ps;
-            if (r >= 0 && r < len + 2 * kHalo) {
-              const int x = x0 - kHalo + r;
-              xs[j] = x;
-              cell[j] = row0 + min(max(x, 0), nx - 1);
-              used[j] = true;
-              out_ok[j] = (r >= kHalo) && (r < kHalo + len);
-            }
+        for (int j = 0; j < kXCells; ++j) {
+          const int r = kXCells * lane + j - ps;
+          if (r >= 0 && r < len + 2 * kHalo) {
+            const int x = x0 - kHalo + r;
+            m.xs[j] = x;
+            m.cell[j] = row0 + min(max(x, 0), nx - 1);
+            m.used[j] = true;
+            m.out_ok[j] = (r >= kHalo) && (r < kHalo + len);
           }
-          ps += len + 2 * kHalo;
-          c += len;
         }
+        ps += len + 2 * kHalo;
+        c += len;
       }
-      T u[kNF][kXCells];
+      return m;
+    };
+    auto load_window = [&](const XMap& m, T (&u)[kNF][kXCells]) {
 #pragma unroll
       for (int q = 0; q < kNF; ++q)
 #pragma unroll
-        for (int j = 0; j < kXCells; ++j) u[q][j] = src[q * pitch + cell[j]];
+        for (int j = 0; j < kXCells; ++j) u[q][j] = src[q * pitch + m.cell[j]];
+    };
+    for (int w = it.a; w < it.a + it.b; ++w) {
+      const XMap m = map_window(w);
+      T u[kNF][kXCells];
+      load_window(m, u);
+      const int (&cell)[kXCells] = m.cell;
+      const int (&xs)[kXCells] = m.xs;
+      const bool (&used)[kXCells] = m.used;
+      const bool (&out_ok)[kXCells] = m.out_ok;
 
       // ---- recovery at U^n
       T ep[kXCells], fE[kXCells], fM[kXCells];
