@@ -44,9 +44,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, decomposition):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources with the same decomposition of the
+    kernel's axis; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -54,7 +55,30 @@ def measured_traffic(kernel, workload):
         d = json.load(fh)
     if d.get("source_hash") != kernel_source_hash():
         return None
+    axis = "xyz".index(kernel[-1])
+    if d.get("decomposition", "").split("/")[axis:axis + 1] != decomposition.split("/")[axis:axis + 1]:
+        return None
     return d.get("bytes_per_launch")
+
+
+def copy_ceiling(torch, B, mib=1024, reps=10):
+    """Achievable HBM bandwidth: the library's plain copy kernel on `mib` MiB,
+    timed with HIP events on the current stream (read + write bytes)."""
+    n = mib << 20
+    src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        B.stream_copy(src, dst, n, st)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        B.stream_copy(src, dst, n, st)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * n / (ms * 1e-3) / 1e9
 
 
 def make_state(torch, B, wl, precision):
@@ -187,7 +211,9 @@ def main():
     dom = max(sweeps, key=lambda k: sweeps[k]["ms_total"])
     per_launch = cells * FIELD_PASSES * esize          # algorithmic bytes
     achieved = per_launch / (sweeps[dom]["avg_us"] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, args.workload)
+    decomposition = format_tiles(s.decomposition())
+    traffic = measured_traffic(dom, args.workload, decomposition)
+    copy_gbs = copy_ceiling(torch, B)
     step_bytes = 3 * per_launch
     rec = {
         "metric": "SHASTA cell-updates/s per step (FP64 vs FP32 vs batched), % HBM roofline",
@@ -210,10 +236,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": dom,
                      "kernel_avg_us": sweeps[dom]["avg_us"],
-                     "bytes_per_launch": per_launch},
+                     "bytes_per_launch": per_launch,
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "step_hbm_frac": value * (step_bytes / cells) / (HBM_PEAK_GBS * 1e9),
         "kernels": prof,
-        "decomposition": format_tiles(s.decomposition()),
+        "decomposition": decomposition,
     }
     red = s.reduce(0)
     rec["check"] = {"nonfinite": red["nonfinite"], "clamp": red["clamp"],

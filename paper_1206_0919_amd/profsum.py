@@ -2,6 +2,8 @@
 
     python -m paper_1206_0919_amd.profsum stats DIR      # --kernel-trace --stats
     python -m paper_1206_0919_amd.profsum pmc DIR [COUNTER...]   # --pmc runs
+    python -m paper_1206_0919_amd.profsum traffic FETCH_DIR WRITE_DIR WORKLOAD \
+        FETCH_SCALE WRITE_SCALE OUT_DIR DECOMPOSITION
 
 Prints a markdown table: per kernel, calls, average duration, and for
 counter runs the average counter value per dispatch.
@@ -90,10 +92,11 @@ def per_dispatch(d, counter):
     return {k: sum(v.values()) / len(v) for k, v in acc.items()}
 
 
-def traffic(fetch_dir, write_dir, workload, fetch_scale, write_scale, out_dir):
+def traffic(fetch_dir, write_dir, workload, fetch_scale, write_scale, out_dir, decomposition):
     """Write profiles/traffic_<kernel>_<workload>.json: HBM bytes per launch
     = fetch_scale * FETCH_SIZE + write_scale * WRITE_SIZE (KiB), tagged with
-    the hash of the kernel sources they were measured on."""
+    the hash of the kernel sources and the decomposition they were measured
+    on."""
     import json
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from bench import kernel_source_hash
@@ -106,7 +109,7 @@ def traffic(fetch_dir, write_dir, workload, fetch_scale, write_scale, out_dir):
         rec = {"kernel": k, "workload": workload, "fetch_KiB": fe[k], "write_KiB": wr[k],
                "fetch_scale": fetch_scale, "write_scale": write_scale,
                "bytes_per_launch": 1024 * (fetch_scale * fe[k] + write_scale * wr[k]),
-               "source_hash": kernel_source_hash()}
+               "source_hash": kernel_source_hash(), "decomposition": decomposition}
         path = os.path.join(out_dir, f"traffic_{base}_{workload}.json")
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=1)
@@ -118,8 +121,8 @@ if __name__ == "__main__":
     if mode == "stats":
         stats(sys.argv[2])
     elif mode == "traffic":
-        # traffic FETCH_DIR WRITE_DIR WORKLOAD FETCH_SCALE WRITE_SCALE OUT_DIR
+        # traffic FETCH_DIR WRITE_DIR WORKLOAD FETCH_SCALE WRITE_SCALE OUT_DIR DECOMPOSITION
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),
-                float(sys.argv[6]), sys.argv[7])
+                float(sys.argv[6]), sys.argv[7], sys.argv[8])
     else:
         pmc(sys.argv[2], sys.argv[3:] or None)
