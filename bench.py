@@ -155,12 +155,15 @@ def format_tiles(dec):
     return "/".join(",".join(str(v) for v in t) for t in dec)
 
 
-def run_workload(torch, B, name, steps, warmup, autotune=True, profile_steps=12, tiles=None):
+def run_workload(torch, B, name, steps, warmup, autotune=True, profile_steps=12, tiles=None,
+                 diff=1.0):
     from paper_1206_0919_amd import inputs
     wl = inputs.workload(name)
     precision = B.FP32_MIXED if wl["precision"] == "fp32" else B.FP64
     s, prims, cells = make_state(torch, B, wl, precision)
     dt = wl["lam"] * wl["dx"]
+    if diff != 1.0:
+        s.set_antidiffusion(diff)
     if tiles is not None:
         s.set_decomposition(tiles)
     elif autotune:
@@ -184,7 +187,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="hotspots200")
     ap.add_argument("--variants", action="store_true",
-                    help="also measure the FP32 and batched workloads")
+                    help="also measure the FP32 and batched workloads and the "
+                         "workload without antiflux")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tiles", default=None,
@@ -262,6 +266,18 @@ def main():
                 "dominant_kernel": vdom, "achieved_GBs": vach,
                 "frac": vach / HBM_PEAK_GBS, "kernels": vprof}
             vs.close()
+        # the paper's runs without anti-flux: same workload, transport only;
+        # the difference is the cost of the antiflux and its limiter
+        nsteps = max(20, args.steps // 5)
+        ns, _, _, ncells, nms, nprof, _ = run_workload(torch, B, args.workload, nsteps,
+                                                       args.warmup, not args.no_autotune,
+                                                       diff=0.0)
+        rec["variants"][args.workload + "_without_antiflux"] = {
+            "value": ncells * nsteps / (nms / 1000.0), "unit": "cell-updates/s",
+            "ms_per_step": nms / nsteps, "steps": nsteps,
+            "antiflux_share_of_step": 1.0 - (nms / nsteps) / rec["ms_per_step"],
+            "kernels": nprof}
+        ns.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(wl, prims)

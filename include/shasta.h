@@ -175,6 +175,17 @@ int shasta_set_persistent(shasta_t* h, int axis, int enable);
 int shasta_get_tiles(const shasta_t* h, int axis, int* p0, int* p1);
 int shasta_get_persistent(const shasta_t* h, int axis, int* enable);
 
+/* Antidiffusion coefficient: the constant diff that scales the phoenical
+ * antiflux A^ph (Sec. 3; Sec. 3.1 and Listing 1 name it), 1 by default.
+ * 0 <= diff
+ * <= 1, else EINVAL.  diff = 0 selects sweep kernels compiled without the
+ * antiflux and its flux limiter (the transport step alone, as the paper's
+ * runs without anti-flux in Sec. 4): their fields equal those of the
+ * limiter kernels at
+ * diff = 0; they always use the grid launch (shasta_set_persistent is then
+ * ignored).  Takes effect at the next shasta_step. */
+int shasta_set_antidiffusion(shasta_t* h, double diff);
+
 /* Time candidate decompositions (tiles and persistent or not) on the device
  * with the given dt, keep the fastest per axis.  A candidate's time is the
  * fastest of three blocks of reps sweeps.  The state is untouched (a sweep

@@ -53,6 +53,7 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "shasta_get_persistent": ([_h, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "shasta_autotune": ([_h, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "shasta_set_antidiffusion": ([_h, ctypes.c_double], ctypes.c_int),
     "shasta_set_graph": ([_h, ctypes.c_int], ctypes.c_int),
     "shasta_set_profiling": ([_h, ctypes.c_int], ctypes.c_int),
     "shasta_read_profile": ([_h, _dp, _i64p], ctypes.c_int),
@@ -208,6 +209,9 @@ class Shasta:
 
     def autotune(self, dt, reps=3):
         _check(self.h, shasta_autotune(self.h, float(dt), int(reps)))
+
+    def set_antidiffusion(self, diff):
+        _check(self.h, shasta_set_antidiffusion(self.h, float(diff)))
 
     def set_graph(self, enable):
         _check(self.h, shasta_set_graph(self.h, int(bool(enable))))

@@ -41,22 +41,6 @@ size_t sweep_args_size();
 
 namespace {
 
-// Kernel arguments of one sweep; must match SweepArgs in the kernels.
-struct SweepArgsHost {
-  const EventDesc* ev;
-  const Item* items;
-  int n_items;
-  int parity;
-  void* field_base;
-  double lam;
-  double diff;
-  double* rec;
-  const int2* xwin;
-  int* counter;
-  const int* order;
-  EosParams eos;
-};
-
 // Axis order of step k: the permutation table of Listing 2.
 const int kBranch[18] = {0, 1, 2, 0, 2, 1, 2, 0, 1, 2, 1, 0, 1, 2, 0, 1, 0, 2};
 
@@ -420,7 +404,7 @@ hipEvent_t take_event(shasta_t* h) {
 }
 
 int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStream_t st) {
-  SweepArgsHost a;
+  SweepArgs a;
   a.ev = dev_events(h);
   a.items = dev_items(h, axis);
   a.n_items = (int)h->items[axis].size();
@@ -429,14 +413,16 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
   a.lam = lam;
   a.diff = h->diff;
   a.rec = dev_rec(h, slot);
-  a.xwin = reinterpret_cast<const int2*>(h->ws + h->off_xwin);
+  a.xwin = reinterpret_cast<const int32_t*>(h->ws + h->off_xwin);
   a.eos = h->eos;
   a.counter = nullptr;
   a.order = nullptr;
+  a.no_antiflux = h->diff == 0.0;
   if (a.n_items == 0) return SHASTA_OK;
   const int per_block = (axis == 0) ? kWavesPerBlock : 1;
   int grid = (a.n_items + per_block - 1) / per_block;
-  if (h->persistent[axis]) {
+  // the kernels without antiflux exist for the grid launch only
+  if (h->persistent[axis] && !a.no_antiflux) {
     const int res = shasta_launch::resident(h->precision == SHASTA_FP32_MIXED, h->eos.kind, axis);
     if (res > 0 && res < grid) {
       grid = res;
@@ -911,6 +897,14 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
   h->profiling = saved_prof;
   drop_graph(h);
   return rc ? rc : rc2;
+}
+
+int shasta_set_antidiffusion(shasta_t* h, double diff) {
+  if (!h) return SHASTA_EINVAL;
+  if (!(diff >= 0.0 && diff <= 1.0)) return fail(h, SHASTA_EINVAL, "diff must lie in [0, 1]");
+  h->diff = diff;
+  drop_graph(h);   // the captured launches carry the old value
+  return SHASTA_OK;
 }
 
 int shasta_set_graph(shasta_t* h, int enable) {

@@ -76,4 +76,22 @@ struct EosParams {
   double e_H;
 };
 
+// Kernel arguments of one sweep (built by the host library).
+struct SweepArgs {
+  const EventDesc* ev;
+  const Item* items;
+  int n_items;
+  int parity;          // buffer holding U^n
+  void* field_base;    // field arrays (T) start here
+  double lam;          // dt / dx
+  double diff;         // antidiffusion scale (1: phoenical)
+  double* rec;         // reduction records of this sweep, one per block
+  const int32_t* xwin; // x sweep: cell range [c0, c1) of every window (pairs)
+  int* counter;        // persistent launch: next work item (null: one block
+                       // or wave per item, no queue)
+  const int* order;    // persistent launch: items in the order they are taken
+  EosParams eos;
+  int no_antiflux;     // 1: kernels without antidiffusion (diff = 0)
+};
+
 }  // namespace shasta

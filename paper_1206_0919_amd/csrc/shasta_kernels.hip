@@ -29,21 +29,15 @@ namespace shasta {
 
 
 
-struct SweepArgs {
-  const EventDesc* ev;
-  const Item* items;
-  int n_items;
-  int parity;          // buffer holding U^n
-  void* field_base;    // field arrays (T) start here
-  double lam;          // dt / dx
-  double diff;         // antidiffusion scale (1: phoenical)
-  double* rec;         // reduction records of this sweep, one per block
-  const int2* xwin;    // x sweep: cell range [c0, c1) of every window
-  int* counter;        // persistent launch: next work item (null: one block
-                       // or wave per item, no queue)
-  const int* order;    // persistent launch: items in the order they are taken
-  EosParams eos;
-};
+
+// The scheme a sweep kernel is compiled for: the EOS kind in the low bits,
+// kNoAntiflux set for the kernels without the phoenical antiflux and its
+// limiter (the transport step alone; the result equals diff = 0).
+constexpr int kNoAntiflux = 16;
+template <int SCHEME>
+constexpr int eos_of = SCHEME & 15;
+template <int SCHEME>
+constexpr bool antiflux_of = (SCHEME & kNoAntiflux) == 0;
 
 // ------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -136,10 +130,10 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 // the bag EOS needs more registers than three pairs allow.
 template <typename T, int EOS>
 struct MarchCfg {
-  static constexpr bool tight = sizeof(T) == 8 && EOS == 0;
+  static constexpr bool tight = sizeof(T) == 8 && eos_of<EOS> == 0;
   static constexpr int sync = tight ? 1 : 2;        // trips between barriers
   static constexpr int prefetch = tight ? 1 : 2;    // rows P loads ahead
-  static constexpr int waves = (sizeof(T) == 8 && EOS == 1) ? 2 : 3;  // per SIMD
+  static constexpr int waves = (sizeof(T) == 8 && eos_of<EOS> == 1) ? 2 : 3;  // per SIMD
   static constexpr int un_slots = 2 * sync + 3;     // U^n rows between P and C
   static_assert(sync == 1 || sync == 2, "the 8-phase loop body needs S in {1, 2}");
   static_assert(prefetch >= 1 && prefetch <= 3, "register ring of 8: lifetime 4 + prefetch");
@@ -204,7 +198,7 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
 #pragma unroll
     for (int q = 0; q < kNF; ++q) L.un[uslot][q][this->lane] = u[q][S0];
     {
-      const Recovered r = recover<EOS>(*this->eos, double(u[0][S0]), double(u[QP][S0]),
+      const Recovered r = recover<eos_of<EOS>>(*this->eos, double(u[0][S0]), double(u[QP][S0]),
                                        double(u[QT1][S0]), double(u[QT2][S0]));
       const double v = r.w * double(u[QP][S0]);
       ep[S0] = T(this->lamh * v);
@@ -226,7 +220,10 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
       hp[q][S1] = transport(kp, s, d[q][S1], d[q][S2], u[q][S1]);        // hat U_{i-1}
       gp[q][S2] = hp[q][S1] - hp[q][S2];                                 // hat Delta_{i-2}
       const T sec = second_difference(d[q][S2], d[q][S4], d[q][S3]);    // at i-3
-      ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], sec, this->diff8);
+      if constexpr (antiflux_of<EOS>)
+        ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], sec, this->diff8);
+      else
+        ap[q][S3] = T(0);
       L.uh[hslot][q][this->lane] = update(hp[q][S3], ap[q][S3], ap[q][S4]);  // U^{n+1/2}_{i-3}
     }
   }
@@ -274,7 +271,7 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
     } else if (EDGE && k >= N) {
       ec[S3] = ec[S4]; fE[S3] = fE[S4]; fM[S3] = fM[S4];
     } else {
-      const Recovered r = recover<EOS>(*this->eos, double(uh[0]), double(uh[QP]),
+      const Recovered r = recover<eos_of<EOS>>(*this->eos, double(uh[0]), double(uh[QP]),
                                        double(uh[QT1]), double(uh[QT2]));
       const double v = r.w * double(uh[QP]);
       ec[S3] = T(this->lam * v);
@@ -318,7 +315,10 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       hc[q][S4] = transport(kc, s, d[q][S4], d[q][S5], u[q][S4]);       // hat U_{i-4}
       if (EDGE && left_edge) hc[q][S5] = hc[q][S4];                      // halo: hat U_{-2}
       gc[q][S5] = hc[q][S4] - hc[q][S5];                                 // hat Delta_{i-5}
-      ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], this->diff8);
+      if constexpr (antiflux_of<EOS>)
+        ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], this->diff8);
+      else
+        ac[q][S6] = T(0);
       const T out = update(hc[q][S6], ac[q][S6], ac[q][S7]);            // U^{n+1}_{i-6}
       if (store) {
         buf_store<T>(dst[q], ooff, out);
@@ -543,8 +543,8 @@ __device__ __forceinline__ void x_coefficients(const T (&eps)[kXCells], const T 
 }
 
 // One 1-D SHASTA application to the 4 owned positions of one field.
-// u: U^n; ul, ur, ur2: U^n at p-1, p+1, p+2.
-template <typename T>
+// u: U^n; ul, ur, ur2: U^n at p-1, p+1, p+2.  AF = false: transport only.
+template <bool AF, typename T>
 __device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCells],
                                       const T (&ur)[kXCells], const T (&ur2)[kXCells],
                                       const Coef<T> (&k)[kXCells], const T (&s)[kXCells],
@@ -557,6 +557,11 @@ __device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCel
     const T dn = ur2[j] - ur[j];     // Delta_{p+1}
     sec[j] = second_difference(dn, dl, dr);
     uh[j] = transport(k[j], s[j], dr, dl, u[j]);
+  }
+  if constexpr (!AF) {
+#pragma unroll
+    for (int j = 0; j < kXCells; ++j) out[j] = update(uh[j], T(0), T(0));
+    return;
   }
   T dh[kXCells];
   {
@@ -602,7 +607,7 @@ void sweep_x(SweepArgs A) {
       dst[q] = field_rsrc(reinterpret_cast<const T*>(A.field_base) + ev.off[A.parity ^ 1] +
                               q * pitch,
                           ev.ncell * (int64_t)sizeof(T));
-    const int2* win = A.xwin + ev.xwin_begin;
+    const int2* win = reinterpret_cast<const int2*>(A.xwin) + ev.xwin_begin;
     const double lam = A.lam;
     const double lamh = 0.5 * lam;
     const T lamsrc_p = T(-0.25 * lam);
@@ -666,7 +671,7 @@ void sweep_x(SweepArgs A) {
       T ep[kXCells], fE[kXCells], fM[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered r = recover<EOS>(A.eos, double(u[0][j]), double(u[QP][j]),
+        const Recovered r = recover<eos_of<EOS>>(A.eos, double(u[0][j]), double(u[QP][j]),
                                          double(u[QT1][j]), double(u[QT2][j]));
         const double v = r.w * double(u[QP][j]);
         ep[j] = T(lamh * v);
@@ -698,14 +703,14 @@ void sweep_x(SweepArgs A) {
           ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0[q] : b_r1[q]);
           s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
         }
-        x_fct(u[q], ul, ur, ur2, k, s, diff8, uh[q]);
+        x_fct<antiflux_of<EOS>>(u[q], ul, ur, ur2, k, s, diff8, uh[q]);
       }
       // ---- recovery at U^{n+1/2}; halo positions take their edge cell's
       //      values (through the wave's LDS table)
       T ec[kXCells], fEc[kXCells], fMc[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered r = recover<EOS>(A.eos, double(uh[0][j]), double(uh[QP][j]),
+        const Recovered r = recover<eos_of<EOS>>(A.eos, double(uh[0][j]), double(uh[QP][j]),
                                          double(uh[QT1][j]), double(uh[QT2][j]));
         const double v = r.w * double(uh[QP][j]);
         ec[j] = T(lam * v);
@@ -749,7 +754,7 @@ void sweep_x(SweepArgs A) {
           ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0[q] : b_r1[q]);
           s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
         }
-        x_fct(u[q], ul, ur, ur2, k, s, diff8, out);
+        x_fct<antiflux_of<EOS>>(u[q], ul, ur, ur2, k, s, diff8, out);
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) {
           buf_store<T>(dst[q], out_ok[j] ? cell[j] * (int)sizeof(T) : kDropOffset, out[j]);
@@ -1058,6 +1063,16 @@ using namespace shasta;
 hipError_t sweep(int fp32, int axis, const void* args, int grid, hipStream_t st) {
   const SweepArgs& a = *static_cast<const SweepArgs*>(args);
   const bool p = a.counter != nullptr;
+  if (a.no_antiflux) {
+    // grid launch only (the host never sets a queue for these kernels)
+    if (p) return hipErrorInvalidValue;
+    constexpr int N = kNoAntiflux;
+    if (a.eos.kind == 0)
+      return fp32 ? launch_sweep<float, N | 0, false>(axis, a, grid, st)
+                  : launch_sweep<double, N | 0, false>(axis, a, grid, st);
+    return fp32 ? launch_sweep<float, N | 1, false>(axis, a, grid, st)
+                : launch_sweep<double, N | 1, false>(axis, a, grid, st);
+  }
   if (a.eos.kind == 0) {
     if (fp32)
       return p ? launch_sweep<float, 0, true>(axis, a, grid, st)

@@ -89,6 +89,10 @@ def test_state_and_eos_validation(b):
     assert b.shasta_set_tiles(h, 2, 32, 48) == b.EINVAL  # lanes not 16/32/64
     assert b.shasta_set_tiles(h, 3, 32, 16) == b.EINVAL
     assert b.shasta_set_tiles(h, 1, 32, 16) == b.OK
+    for bad_diff in (-0.1, 1.5, float("nan"), float("inf")):
+        assert b.shasta_set_antidiffusion(h, bad_diff) == b.EINVAL
+    for diff in (0.0, 0.5, 1.0):
+        assert b.shasta_set_antidiffusion(h, diff) == b.OK
     out = (ctypes.c_double * 12)()
     cnt = (ctypes.c_int64 * 4)()
     assert b.shasta_reduce(h, 1, out, cnt) == b.EINVAL

@@ -120,6 +120,30 @@ def test_hotspots_fp64_vs_oracle(B, torch, orc, dims, steps, seed):
     assert red["clamp"] == 0 and red["floor"] == 0 and red["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("diff", [0.0, 0.5])
+def test_antidiffusion_scale_vs_oracle(B, torch, orc, diff):
+    # diff = 0.5 runs the limiter kernels with a scaled antiflux; diff = 0
+    # runs the kernels compiled without antiflux and limiter (transport only)
+    dims, steps, seed = (37, 50, 29), 8, 5
+    rng = np.random.default_rng(seed)
+    pr = inputs.hotspots(dims, DX, 6, seed=seed)
+    v = rng.uniform(-0.5, 0.5, (3,) + pr.e.shape) / np.sqrt(3)
+    prim = inputs.Primitive(pr.e, v[0], v[1], v[2], pr.n)
+    s = gpu_state(B, torch, prim)
+    s.set_antidiffusion(diff)
+    s.set_step_index(seed)
+    s.step(DT, steps)
+    got = read_np(s)
+    U = to_cons(orc, prim)
+    ledger, _, _ = orc.run(U, LAM, steps, k0=seed, diff=diff)
+    errs = rel_errors(got, U)
+    print("diff", diff, "rel errors", errs)
+    assert max(errs) <= TOL64
+    red = s.reduce()
+    np.testing.assert_allclose(red["outflow"], ledger, rtol=1e-11,
+                               atol=1e-12 * np.abs(ledger).max())
+
+
 def test_single_cell_and_thin_grids(B, torch, orc):
     for dims in ((1, 1, 1), (1, 5, 3), (7, 1, 2), (3, 3, 70)):
         rng = np.random.default_rng(sum(dims))

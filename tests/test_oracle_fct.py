@@ -21,6 +21,20 @@ def test_phoenical_identity_at_rest(orc):
         np.testing.assert_allclose(out[3:-3], u[3:-3], rtol=4e-16, atol=0)
 
 
+@pytest.mark.parametrize("diff", [0.0, 0.25, 0.5, 1.0])
+def test_antidiffusion_scale_at_rest(orc, diff):
+    # At rest hat U = U + D2/8 (D2 = U_{j+1} - 2 U_j + U_{j-1}) and the
+    # phoenical antiflux is diff/8 Delta_j; on smooth monotone data the
+    # limiter is inactive, so U^{n+1} = U + (1 - diff) D2 / 8: diff = 0 is
+    # the bare SHASTA diffusion with coefficient 1/8, diff = 1 removes it.
+    x = np.linspace(-1.0, 1.0, 48)
+    for u in (np.tanh(x) + 2.0, 3.0 + x + 0.1 * x ** 3, np.exp(x)):
+        out, _ = orc.fct_1d(with_halo(u), np.zeros(u.size + 6), None, 0.0, diff=diff)
+        d2 = u[4:-2] - 2.0 * u[3:-3] + u[2:-4]
+        np.testing.assert_allclose(out[3:-3], u[3:-3] + (1.0 - diff) * d2 / 8.0,
+                                   rtol=1e-15, atol=1e-15)
+
+
 def test_step_at_rest_is_preserved_exactly(orc):
     # Hand-derived worked example: a step at rest gets hat U = (..,1/8,7/8,..)
     # and antiflux A = 1/8 at the jump, so U^{n+1} equals U^n exactly.

@@ -23,6 +23,7 @@ MUTANTS = {
     "transposed_delta": ("0.5 * Qp[P(j)] * Qp[P(j)] * D[P(j)] -", "0.5 * Qp[P(j)] * Qp[P(j)] * D[P(j - 1)] -"),
     "qsum_dropped": ("(Qp[P(j)] + Qm[P(j)]) * U[P(j)]", "U[P(j)]"),
     "antidiffusion_coeff": ("(diff / 8.0)", "(diff / 6.0)"),
+    "antidiffusion_ignores_diff": ("(diff / 8.0)", "(1.0 / 8.0)"),
     "second_difference_coeff": ("second / 8.0", "second / 4.0"),
     "limiter_drops_term": ("fmin(fmin(s * Dh[P(j + 1)], fabs(Aph)), s * Dh[P(j - 1)])", "fmin(s * Dh[P(j + 1)], fabs(Aph))"),
     "limiter_wrong_neighbour": ("s * Dh[P(j - 1)])", "s * Dh[P(j)])"),
@@ -48,6 +49,7 @@ PINS = [
     lambda o, ob: tr.test_prim_cons_round_trip(o),
     lambda o, ob: tf.test_phoenical_identity_at_rest(o),
     lambda o, ob: tf.test_step_at_rest_is_preserved_exactly(o),
+    lambda o, ob: [tf.test_antidiffusion_scale_at_rest(o, d) for d in (0.0, 0.5)],
     lambda o, ob: [tf.test_boundary_flux_closes_the_sum(o, s, h) for s in (0, 1) for h in (False, True)],
     lambda o, ob: [tf.test_passive_scalar_no_new_extrema(o, e) for e in (0.2, -0.2)],
     lambda o, ob: tp.test_shock_tube_vs_exact(o, 50),
