@@ -31,6 +31,7 @@ CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
 
 EOS_IDEAL = 0
 EOS_BAG = 1
+EOS_TABLE = 2
 
 
 def build(src: str = _SRC, out: str = _LIB, extra=()) -> str:
@@ -42,7 +43,9 @@ def build(src: str = _SRC, out: str = _LIB, extra=()) -> str:
 
 class _Eos(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("B", ctypes.c_double),
-                ("e_H", ctypes.c_double)]
+                ("e_H", ctypes.c_double), ("n", ctypes.c_int),
+                ("te", ctypes.POINTER(ctypes.c_double)),
+                ("tp", ctypes.POINTER(ctypes.c_double))]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -96,16 +99,24 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_dp)
 
 
-def make_eos(kind: int = EOS_IDEAL, B: float = 0.0, e_H: float = 0.0) -> _Eos:
-    return _Eos(int(kind), float(B), float(e_H))
+def make_eos(kind: int = EOS_IDEAL, B: float = 0.0, e_H: float = 0.0, table=None):
+    """EOS descriptor; for EOS_TABLE, table = (node energy densities, node
+    pressures).  Returns (descriptor, arrays it points into)."""
+    if kind == EOS_TABLE:
+        te = np.ascontiguousarray(table[0], dtype=np.float64)
+        tp = np.ascontiguousarray(table[1], dtype=np.float64)
+        assert te.size == tp.size >= 2
+        return _Eos(int(kind), 0.0, 0.0, te.size, _ptr(te), _ptr(tp)), (te, tp)
+    return _Eos(int(kind), float(B), float(e_H), 0, None, None), ()
 
 
 class Oracle:
     """Thin ctypes front end; state lives in numpy arrays owned by the caller."""
 
-    def __init__(self, eos_kind=EOS_IDEAL, B=0.0, e_H=0.0, lib_path=_LIB):
+    def __init__(self, eos_kind=EOS_IDEAL, B=0.0, e_H=0.0, lib_path=_LIB, table=None):
+        self.lib_path = lib_path
         self.lib = load(lib_path)
-        self.eos = make_eos(eos_kind, B, e_H)
+        self.eos, self._keep = make_eos(eos_kind, B, e_H, table)
 
     # eq. (cf-*) and the EOS closure
     def pressure(self, e: float) -> float:

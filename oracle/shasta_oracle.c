@@ -56,15 +56,34 @@ enum { ORC_NF = 5 };
  * (Sec. 2, closure "ideal gas").  kind 1: bag model with a first order phase
  * transition: p = e/3 below e_H, p = e_H/3 in the mixed phase
  * e_H < e < e_Q = e_H + 4B, p = (e - 4B)/3 above (the paper leaves the EOS
- * open and mentions tabled ones; this is the standard bag closure). */
+ * open and mentions tabled ones; this is the standard bag closure).
+ * kind 2: tabled EOS (Sec. 2 and Sec. 3, last paragraph: a tabulated p(e)
+ * read through an interpolation, the reason the recovery is a root search):
+ * nodes te[0] = 0 < te[1] < ... < te[n-1] with pressures tp[k], p(e) linear
+ * between neighbouring nodes and the last segment continued beyond te[n-1]. */
 typedef struct {
   int kind;
   double B;
   double e_H;
+  int n;             /* kind 2: number of nodes (>= 2) */
+  const double* te;  /* kind 2: node energy densities */
+  const double* tp;  /* kind 2: node pressures */
 } orc_eos;
 
 double orc_pressure(const orc_eos* eos, double e) {
   if (eos->kind == 0) return e / 3.0;
+  if (eos->kind == 2) {
+    /* segment k with te[k] <= e < te[k+1], by bisection over the nodes;
+     * k = n-2 for e >= te[n-2] (the last segment, extended) */
+    int lo = 0, hi = eos->n - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (eos->te[mid] <= e) lo = mid; else hi = mid;
+    }
+    const int k = lo;
+    const double slope = (eos->tp[k + 1] - eos->tp[k]) / (eos->te[k + 1] - eos->te[k]);
+    return eos->tp[k] + slope * (e - eos->te[k]);
+  }
   const double e_Q = eos->e_H + 4.0 * eos->B;
   if (e <= eos->e_H) return e / 3.0;
   if (e < e_Q) return eos->e_H / 3.0;

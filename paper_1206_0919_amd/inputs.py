@@ -131,6 +131,33 @@ def bag_parameters(B_quarter_GeV=0.235, d_H=3.0, d_Q=37.0):
     return B, e_H
 
 
+def crossover_eos_table(n_nodes=48, B=None, e_c=1.0, width=1.0, e_max=1.0e3):
+    """Synthetic tabled EOS (node energy densities, node pressures), GeV/fm^3.
+
+    A smooth crossover from the massless gas p = e/3 to the bag-shifted
+    plasma p = (e - 4B)/3: p(e) = e/3 - (4B/3) (s(e) - s(0)) with the step
+    s(e) = (1 + tanh((e - e_c)/width)) / 2, sampled at e = 0 and at
+    n_nodes - 1 log-spaced points in [1e-3, e_max].  For width >= 2B the
+    slope dp/de stays in (0, 1/3], so the table is causal and p increases.
+    """
+    if B is None:
+        B, _ = bag_parameters()
+    e = np.concatenate([[0.0], np.geomspace(1e-3, e_max, n_nodes - 1)])
+    step = lambda x: 0.5 * (1.0 + np.tanh((x - e_c) / width))
+    p = e / 3.0 - (4.0 * B / 3.0) * (step(e) - step(0.0))
+    return e, p
+
+
+def bag_eos_table(B, e_H, e_top=1.0e3):
+    """The bag model of bag_parameters() as a table: its break points e_H and
+    e_Q = e_H + 4B plus one node far in the plasma phase (the last segment,
+    extended, is the plasma line p = (e - 4B)/3)."""
+    e_Q = e_H + 4.0 * B
+    e = np.array([0.0, e_H, e_Q, e_top])
+    p = np.array([0.0, e_H / 3.0, e_H / 3.0, (e_top - 4.0 * B) / 3.0])
+    return e, p
+
+
 # ---------------------------------------------------------------- workloads
 # The five synthetic workloads, by name.  Each returns dims, dx, dt/dx, steps,
 # precision, EOS, and a callable producing the primitive state.

@@ -9,6 +9,7 @@ import os
 import pytest
 
 import oracle
+from paper_1206_0919_amd import inputs
 import test_oracle_fct as tf
 import test_oracle_physics as tp
 import test_oracle_recovery as tr
@@ -41,12 +42,18 @@ MUTANTS = {
     "energy_definition": ("E[i] = (e[i] + p * v2) * g2;", "E[i] = (e[i] + p) * g2;"),
     "velocity_direction": ("*vy = v * My / M;", "*vy = v * Mx / M;"),
     "bag_mixed_phase": ("if (e < e_Q) return eos->e_H / 3.0;", "if (e < e_Q) return e / 3.0;"),
+    "table_wrong_anchor": ("return eos->tp[k] + slope * (e - eos->te[k]);",
+                           "return eos->tp[k] + slope * (e - eos->te[k + 1]);"),
+    "table_search_off_by_one": ("if (eos->te[mid] <= e) lo = mid; else hi = mid;",
+                                "if (eos->te[mid + 1] <= e) lo = mid; else hi = mid;"),
 }
 
 PINS = [
     lambda o, ob: tr.test_recovery_ideal_closed_form(o),
     lambda o, ob: tr.test_recovery_bag_closed_form(ob),
     lambda o, ob: tr.test_prim_cons_round_trip(o),
+    lambda o, ob: tr.check_table_closed_form(
+        oracle.Oracle(oracle.EOS_TABLE, table=inputs.crossover_eos_table(), lib_path=o.lib_path)),
     lambda o, ob: tf.test_phoenical_identity_at_rest(o),
     lambda o, ob: tf.test_step_at_rest_is_preserved_exactly(o),
     lambda o, ob: [tf.test_antidiffusion_scale_at_rest(o, d) for d in (0.0, 0.5)],

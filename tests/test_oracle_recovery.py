@@ -83,6 +83,76 @@ def test_recovery_bag_closed_form(orc_bag):
     assert hit == {0, 1, 2}
 
 
+def _table_branches(te, tp):
+    """(a, b, e_lo, e_hi) of every segment of a piecewise linear table; the
+    last segment extends to infinity."""
+    out = []
+    for k in range(len(te) - 1):
+        a = (tp[k + 1] - tp[k]) / (te[k + 1] - te[k])
+        hi = te[k + 1] if k < len(te) - 2 else np.inf
+        out.append((a, tp[k] - a * te[k], te[k], hi))
+    return out
+
+
+def _table_oracle(table):
+    import oracle
+    return oracle.Oracle(oracle.EOS_TABLE, table=table)
+
+
+def test_table_pressure_is_the_interpolant():
+    from paper_1206_0919_amd import inputs
+    te, tp = inputs.crossover_eos_table()
+    o = _table_oracle((te, tp))
+    rng = np.random.default_rng(11)
+    pts = np.concatenate([te, 10 ** rng.uniform(-4, 3.3, 500), [2.5e3, 1e4]])
+    a_last = (tp[-1] - tp[-2]) / (te[-1] - te[-2])
+    for e in pts:
+        ref = np.interp(e, te, tp) if e <= te[-1] else tp[-1] + a_last * (e - te[-1])
+        assert o.pressure(e) == pytest.approx(ref, rel=1e-15, abs=1e-300)
+    # the synthetic table is causal and monotone
+    slopes = np.diff(tp) / np.diff(te)
+    assert np.all(slopes > 0.0) and np.all(slopes <= 1.0 / 3.0 + 1e-15)
+
+
+def test_recovery_table_closed_form():
+    from paper_1206_0919_amd import inputs
+    check_table_closed_form(_table_oracle(inputs.crossover_eos_table()))
+
+
+def check_table_closed_form(o):
+    # tabled EOS (Sec. 2, Sec. 3 last paragraph): the fixed point converges to
+    # the closed-form root of the segment that holds e
+    from paper_1206_0919_amd import inputs
+    te, tp = inputs.crossover_eos_table()
+    branches = _table_branches(te, tp)
+    rng = np.random.default_rng(12)
+    E = np.concatenate([10 ** rng.uniform(-3, 3.5, 500), te[1:] * 1.02])
+    r = rng.uniform(0, 0.99, E.size)
+    segs = set()
+    for Ei, ri in zip(E, r):
+        M = ri * Ei
+        res = o.recover(Ei, 0.0, M, 0.0)
+        v_ex, e_ex = closed_form_v(Ei, M, branches)
+        segs.add(int(np.searchsorted(te, e_ex)))
+        assert res["converged"]
+        assert abs(res["v"] - v_ex) <= 4e-15 * max(v_ex, 1e-300) + 1e-300
+        assert abs(res["e"] - e_ex) <= 1e-14 * Ei
+    assert len(segs) >= 30   # most segments, and the extended last one, are hit
+
+
+def test_table_through_bag_break_points_is_the_bag_model(orc_bag):
+    from paper_1206_0919_amd import inputs
+    B, e_H = orc_bag.eos.B, orc_bag.eos.e_H
+    o = _table_oracle(inputs.bag_eos_table(B, e_H))
+    rng = np.random.default_rng(13)
+    E = np.concatenate([10 ** rng.uniform(-3, 3.5, 300), rng.uniform(0.5 * e_H, 4 * e_H + 8 * B, 300)])
+    for Ei, ri in zip(E, rng.uniform(0, 0.99, E.size)):
+        a = o.recover(Ei, ri * Ei, 0.0, 0.0)
+        b = orc_bag.recover(Ei, ri * Ei, 0.0, 0.0)
+        assert a["v"] == pytest.approx(b["v"], rel=4e-15, abs=1e-300)
+        assert a["p"] == pytest.approx(b["p"], rel=1e-14, abs=1e-15 * Ei)
+
+
 def test_guard_clamp_and_floor(orc):
     # |M| >= E: clamped to (1 - 1e-10) E, direction kept, counted
     res = orc.recover(1.0, 2.0, 0.0, 0.0)
