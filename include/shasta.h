@@ -54,6 +54,7 @@ typedef struct shasta_handle shasta_t;
 #define SHASTA_EOS_IDEAL 0 /* p = e/3 (Sec. 2, ideal gas)                    */
 #define SHASTA_EOS_BAG 1   /* bag model: p = e/3 (e <= e_H), e_H/3 in the
                               mixed phase, (e - 4B)/3 (e >= e_H + 4B)        */
+#define SHASTA_EOS_TABLE 2 /* tabulated p(e), linear between nodes          */
 
 /* field indices for shasta_read_field */
 #define SHASTA_FIELD_E 0
@@ -94,7 +95,14 @@ int shasta_bind_workspace(shasta_t* h, void* dev_ptr, size_t bytes);
 
 /* Select the EOS.  SHASTA_EOS_IDEAL takes no parameters (n_params = 0);
  * SHASTA_EOS_BAG takes params = {B, e_H} in GeV/fm^3, both > 0 and finite
- * (e_Q = e_H + 4B is derived). */
+ * (e_Q = e_H + 4B is derived).  SHASTA_EOS_TABLE (a tabulated p(e) read
+ * through an interpolation, Sec. 2 and Sec. 3, last paragraph) takes
+ * params = {e_0, ..., e_{m-1}, p_0, ..., p_{m-1}}, n_params = 2m,
+ * 2 <= m <= 1024, host memory, copied: e_0 = 0 < e_1 < ... (GeV/fm^3),
+ * p_k >= 0, finite, every slope (p_{k+1} - p_k)/(e_{k+1} - e_k) in [0, 1];
+ * p is linear between neighbouring nodes and the last segment continues
+ * past e_{m-1}.  EINVAL on any violation (the previous EOS stays).  May be
+ * called before or after shasta_bind_workspace. */
 int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params);
 
 /* Write the state of event ev from primitive fields (device pointers to

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("SHASTA_LIB") or os.path.join(HERE, "lib", "libshasta.
 OK, EINVAL, ESTATE, EWORKSPACE, EHIP, ENONFINITE, ENOCONVERGE = range(7)
 FP64, FP32_MIXED = 0, 1
 BC_OUTFLOW = 0
-EOS_IDEAL, EOS_BAG = 0, 1
+EOS_IDEAL, EOS_BAG, EOS_TABLE = 0, 1, 2
 FIELDS = ("E", "Mx", "My", "Mz", "R", "e", "p", "vx", "vy", "vz", "n")
 
 if not os.path.exists(LIB_PATH):
@@ -128,8 +128,13 @@ class Shasta:
 
     # -- calls
     def set_eos(self, kind, params=()):
+        params = [float(x) for x in params]
         arr = (ctypes.c_double * max(1, len(params)))(*params)
         _check(self.h, shasta_set_eos(self.h, int(kind), arr, len(params)))
+
+    def set_eos_table(self, e_nodes, p_nodes):
+        """Tabled EOS: node energy densities (from 0, increasing) and pressures."""
+        self.set_eos(EOS_TABLE, list(e_nodes) + list(p_nodes))
 
     def _dev(self, a, ev):
         t = self.torch

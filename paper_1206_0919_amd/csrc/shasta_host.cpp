@@ -60,7 +60,8 @@ struct shasta_handle {
   int precision = 0;
   int bc = 0;
   hipStream_t stream = nullptr;
-  EosParams eos{0, 0, 0.0, 0.0};
+  EosParams eos{0, 0, 0.0, 0.0, nullptr};
+  std::vector<double> eos_tab;   // tabled EOS: the 4 m doubles of EosParams::tab
   double diff = 1.0;
 
   // decomposition (0 = automatic per event)
@@ -84,7 +85,7 @@ struct shasta_handle {
   size_t elem = 8;
   size_t field_bytes = 0, off_ev = 0, off_items[3] = {0, 0, 0}, off_rec = 0,
          off_acc = 0, off_scratch = 0, off_xwin = 0, off_cnt = 0, off_order[3] = {0, 0, 0},
-         off_part = 0, total = 0;
+         off_part = 0, off_eos = 0, total = 0;
   char* ws = nullptr;
   size_t ws_len = 0;
 
@@ -337,6 +338,8 @@ void layout(shasta_t* h) {
   h->fin_cap = (h->item_cap[0] + h->item_cap[1] + h->item_cap[2]) / kFinChunk + h->n_events;
   h->off_part = p;
   p = align256(p + sizeof(double) * R_SIZE * (size_t)h->fin_cap);
+  h->off_eos = p;   // tabled EOS, largest table
+  p = align256(p + sizeof(double) * 4 * (size_t)kMaxEosNodes);
   for (int ax = 0; ax < 3; ++ax) {
     h->off_order[ax] = p;
     p = align256(p + sizeof(int) * (size_t)h->item_cap[ax]);
@@ -354,6 +357,18 @@ double* dev_acc(shasta_t* h, int ev) {
 }
 char* dev_field(shasta_t* h, int ev, int buf) {
   return h->ws + (size_t)h->evd[ev].off[buf] * h->elem;
+}
+
+// Copy the tabled EOS into the workspace and point the EOS parameters at it
+// (nothing to do for the analytic EOS or before a workspace is bound).
+int upload_eos(shasta_t* h) {
+  if (h->eos.kind != SHASTA_EOS_TABLE || !h->ws) return SHASTA_OK;
+  double* dev = reinterpret_cast<double*>(h->ws + h->off_eos);
+  HIPCHECK(h, hipMemcpyAsync(dev, h->eos_tab.data(), sizeof(double) * h->eos_tab.size(),
+                             hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
+  h->eos.tab = dev;
+  return SHASTA_OK;
 }
 
 int upload_tables(shasta_t* h) {
@@ -593,6 +608,7 @@ int shasta_bind_workspace(shasta_t* h, void* dev_ptr, size_t bytes) {
   h->parity = 0;
   int rc = upload_tables(h);
   if (rc) return rc;
+  if ((rc = upload_eos(h))) return rc;
   HIPCHECK(h, shasta_launch::zero(dev_acc(h, 0), (int64_t)A_SIZE * h->n_events, h->stream));
   HIPCHECK(h, hipStreamSynchronize(h->stream));
   return SHASTA_OK;
@@ -602,13 +618,42 @@ int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params) {
   if (!h) return SHASTA_EINVAL;
   if (kind == SHASTA_EOS_IDEAL) {
     if (n_params != 0) return fail(h, SHASTA_EINVAL, "ideal EOS takes no parameters");
-    h->eos = EosParams{0, 0, 0.0, 0.0};
+    h->eos = EosParams{0, 0, 0.0, 0.0, nullptr};
   } else if (kind == SHASTA_EOS_BAG) {
     if (n_params != 2 || !params) return fail(h, SHASTA_EINVAL, "bag EOS takes {B, e_H}");
     const double B = params[0], eH = params[1];
     if (!(B > 0.0) || !(eH > 0.0) || !std::isfinite(B) || !std::isfinite(eH))
       return fail(h, SHASTA_EINVAL, "bag EOS needs B > 0 and e_H > 0");
-    h->eos = EosParams{1, 0, B, eH};
+    h->eos = EosParams{1, 0, B, eH, nullptr};
+  } else if (kind == SHASTA_EOS_TABLE) {
+    if (!params || n_params < 4 || n_params % 2 || n_params / 2 > kMaxEosNodes)
+      return fail(h, SHASTA_EINVAL, "tabled EOS takes {e_0..e_m-1, p_0..p_m-1}, 2 <= m <= " +
+                                        std::to_string(kMaxEosNodes));
+    const int m = n_params / 2;
+    const double* te = params;
+    const double* tp = params + m;
+    if (te[0] != 0.0) return fail(h, SHASTA_EINVAL, "tabled EOS: the first node must be e = 0");
+    std::vector<double> tab(4 * (size_t)m);
+    for (int k = 0; k < m; ++k) {
+      if (!std::isfinite(te[k]) || !std::isfinite(tp[k]) || !(tp[k] >= 0.0))
+        return fail(h, SHASTA_EINVAL, "tabled EOS: nodes must be finite with p >= 0");
+      if (k > 0 && !(te[k] > te[k - 1]))
+        return fail(h, SHASTA_EINVAL, "tabled EOS: node energies must increase");
+      tab[k] = te[k];
+      tab[m + k] = tp[k];
+    }
+    for (int k = 0; k + 1 < m; ++k) {
+      const double a = (tp[k + 1] - tp[k]) / (te[k + 1] - te[k]);
+      if (!(a >= 0.0 && a <= 1.0))
+        return fail(h, SHASTA_EINVAL, "tabled EOS: slopes dp/de must lie in [0, 1]");
+      tab[2 * m + k] = a;
+      tab[3 * m + k] = tp[k] - a * te[k];
+    }
+    tab[3 * m - 1] = tab[3 * m - 2];   // the last segment continues past the last node
+    tab[4 * m - 1] = tab[4 * m - 2];
+    h->eos_tab.swap(tab);
+    h->eos = EosParams{2, m, 0.0, 0.0, nullptr};
+    if (int rc = upload_eos(h)) return rc;
   } else {
     return fail(h, SHASTA_EINVAL, "unknown EOS kind");
   }

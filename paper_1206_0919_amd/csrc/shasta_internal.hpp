@@ -69,11 +69,17 @@ struct Item {
   int32_t pad[2];
 };
 
+constexpr int kMaxEosNodes = 1024;   // tabled EOS: most nodes
+
 struct EosParams {
-  int32_t kind;  // 0 ideal, 1 bag
-  int32_t pad;
+  int32_t kind;  // 0 ideal, 1 bag, 2 table
+  int32_t n;     // table: nodes m
   double B;
   double e_H;
+  // table: 4 m doubles in device memory: node e_k (m), node p_k (m), and the
+  // slope a_k and intercept b_k of segment k = [e_k, e_k+1] (p = a e + b;
+  // entry m-1 repeats segment m-2, which continues past the last node)
+  const double* tab;
 };
 
 // Kernel arguments of one sweep (built by the host library).

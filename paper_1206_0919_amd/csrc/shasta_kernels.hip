@@ -127,13 +127,13 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 // runs three pairs per SIMD: 168 registers and 23 KB of LDS per pair, which
 // needs a barrier every trip (S = 1) and one row of prefetch.  The others
 // keep S = 2 and two rows of prefetch: FP32 fits three pairs anyway, FP64 on
-// the bag EOS needs more registers than three pairs allow.
+// the bag and tabled EOS need more registers than three pairs allow.
 template <typename T, int EOS>
 struct MarchCfg {
   static constexpr bool tight = sizeof(T) == 8 && eos_of<EOS> == 0;
   static constexpr int sync = tight ? 1 : 2;        // trips between barriers
   static constexpr int prefetch = tight ? 1 : 2;    // rows P loads ahead
-  static constexpr int waves = (sizeof(T) == 8 && eos_of<EOS> == 1) ? 2 : 3;  // per SIMD
+  static constexpr int waves = (sizeof(T) == 8 && eos_of<EOS> != 0) ? 2 : 3;  // per SIMD
   static constexpr int un_slots = 2 * sync + 3;     // U^n rows between P and C
   static_assert(sync == 1 || sync == 2, "the 8-phase loop body needs S in {1, 2}");
   static_assert(prefetch >= 1 && prefetch <= 3, "register ring of 8: lifetime 4 + prefetch");
@@ -914,6 +914,8 @@ __global__ void prim_to_cons(EosParams eos, const double* e, const double* vx,
     double p;
     if (eos.kind == 0) {
       p = ei * kThird;
+    } else if (eos.kind == 2) {
+      p = table_pressure(eos, ei);
     } else {
       const double eQ = eos.e_H + 4.0 * eos.B;
       p = (ei <= eos.e_H) ? ei * kThird
@@ -956,8 +958,9 @@ __global__ void read_out(EosParams eos, const T* in, int64_t pitch, int64_t ncel
     }
     const double E = in[i], Mx = in[pitch + i], My = in[2 * pitch + i],
                  Mz = in[3 * pitch + i], R = in[4 * pitch + i];
-    const Recovered r = (eos.kind == 0) ? recover<0>(eos, E, Mx, My, Mz)
-                                        : recover<1>(eos, E, Mx, My, Mz);
+    const Recovered r = (eos.kind == 0)   ? recover<0>(eos, E, Mx, My, Mz)
+                        : (eos.kind == 1) ? recover<1>(eos, E, Mx, My, Mz)
+                                          : recover<2>(eos, E, Mx, My, Mz);
     double out;
     switch (field) {
       case 5: out = r.e; break;
@@ -1060,6 +1063,22 @@ int resident_blocks(int axis) {
 namespace shasta_launch {
 using namespace shasta;
 
+template <int S>
+hipError_t sweep_scheme(int fp32, int axis, const SweepArgs& a, int grid, bool p,
+                        hipStream_t st) {
+  if (fp32)
+    return p ? launch_sweep<float, S, true>(axis, a, grid, st)
+             : launch_sweep<float, S, false>(axis, a, grid, st);
+  return p ? launch_sweep<double, S, true>(axis, a, grid, st)
+           : launch_sweep<double, S, false>(axis, a, grid, st);
+}
+
+template <int S>
+hipError_t sweep_scheme_grid(int fp32, int axis, const SweepArgs& a, int grid, hipStream_t st) {
+  return fp32 ? launch_sweep<float, S, false>(axis, a, grid, st)
+              : launch_sweep<double, S, false>(axis, a, grid, st);
+}
+
 hipError_t sweep(int fp32, int axis, const void* args, int grid, hipStream_t st) {
   const SweepArgs& a = *static_cast<const SweepArgs*>(args);
   const bool p = a.counter != nullptr;
@@ -1067,30 +1086,28 @@ hipError_t sweep(int fp32, int axis, const void* args, int grid, hipStream_t st)
     // grid launch only (the host never sets a queue for these kernels)
     if (p) return hipErrorInvalidValue;
     constexpr int N = kNoAntiflux;
-    if (a.eos.kind == 0)
-      return fp32 ? launch_sweep<float, N | 0, false>(axis, a, grid, st)
-                  : launch_sweep<double, N | 0, false>(axis, a, grid, st);
-    return fp32 ? launch_sweep<float, N | 1, false>(axis, a, grid, st)
-                : launch_sweep<double, N | 1, false>(axis, a, grid, st);
+    switch (a.eos.kind) {
+      case 0: return sweep_scheme_grid<N | 0>(fp32, axis, a, grid, st);
+      case 1: return sweep_scheme_grid<N | 1>(fp32, axis, a, grid, st);
+      case 2: return sweep_scheme_grid<N | 2>(fp32, axis, a, grid, st);
+      default: return hipErrorInvalidValue;
+    }
   }
-  if (a.eos.kind == 0) {
-    if (fp32)
-      return p ? launch_sweep<float, 0, true>(axis, a, grid, st)
-               : launch_sweep<float, 0, false>(axis, a, grid, st);
-    return p ? launch_sweep<double, 0, true>(axis, a, grid, st)
-             : launch_sweep<double, 0, false>(axis, a, grid, st);
+  switch (a.eos.kind) {
+    case 0: return sweep_scheme<0>(fp32, axis, a, grid, p, st);
+    case 1: return sweep_scheme<1>(fp32, axis, a, grid, p, st);
+    case 2: return sweep_scheme<2>(fp32, axis, a, grid, p, st);
+    default: return hipErrorInvalidValue;
   }
-  if (fp32)
-    return p ? launch_sweep<float, 1, true>(axis, a, grid, st)
-             : launch_sweep<float, 1, false>(axis, a, grid, st);
-  return p ? launch_sweep<double, 1, true>(axis, a, grid, st)
-           : launch_sweep<double, 1, false>(axis, a, grid, st);
 }
 
 int resident(int fp32, int eos_kind, int axis) {
-  if (eos_kind == 0)
-    return fp32 ? resident_blocks<float, 0>(axis) : resident_blocks<double, 0>(axis);
-  return fp32 ? resident_blocks<float, 1>(axis) : resident_blocks<double, 1>(axis);
+  switch (eos_kind) {
+    case 0: return fp32 ? resident_blocks<float, 0>(axis) : resident_blocks<double, 0>(axis);
+    case 1: return fp32 ? resident_blocks<float, 1>(axis) : resident_blocks<double, 1>(axis);
+    case 2: return fp32 ? resident_blocks<float, 2>(axis) : resident_blocks<double, 2>(axis);
+    default: return 0;
+  }
 }
 
 hipError_t finalize(const EventDesc* ev, int n_events, int max_chunks,

@@ -90,14 +90,49 @@ __device__ __forceinline__ void ideal_root_scaled(double E, double M2,
   e = __builtin_ldexp(es, k);
 }
 
+// Root of a linear EOS branch p = a e + b (a >= 0): w = v/|M| and e.  The
+// root is homogeneous of degree 0 in (E, M, b) for w E, so the squares are
+// kept in the normal range by a power-of-two scaling of all three.
+__device__ __forceinline__ void linear_root(double a, double b, double E, double M2,
+                                            double& w, double& e) {
+  const double K = __builtin_fma(1.0 + a, E, b);
+  const double disc = fmax(__builtin_fma(K, K, -4.0 * a * M2), 0.0);
+  w = 2.0 * rcp(K + sqrt_pos(disc));
+  e = __builtin_fma(-M2, w, E);
+}
+__device__ __forceinline__ void linear_root_scaled(double a, double b, double E, double M2,
+                                                   double& w, double& e) {
+  const int k = __builtin_amdgcn_frexp_exp(E);
+  double ws, es;
+  linear_root(a, __builtin_ldexp(b, -k), __builtin_ldexp(E, -k), __builtin_ldexp(M2, -2 * k),
+              ws, es);
+  w = __builtin_ldexp(ws, -k);
+  e = __builtin_ldexp(es, k);
+}
+
+// Tabled EOS: segment of node e_k that holds e (largest k <= m-2 with
+// e_k <= e), by a search with the same trip count in every lane.
+__device__ __forceinline__ int table_segment_of_e(const EosParams& eos, double e) {
+  const int m = eos.n;
+  int k = 0;
+  for (int step = 1 << (31 - __builtin_clz(m - 1)); step > 0; step >>= 1)
+    if (k + step <= m - 2 && eos.tab[k + step] <= e) k += step;
+  return k;
+}
+__device__ __forceinline__ double table_pressure(const EosParams& eos, double e) {
+  const int k = table_segment_of_e(eos, e);
+  return __builtin_fma(eos.tab[2 * eos.n + k], e, eos.tab[3 * eos.n + k]);
+}
+
 // True if any lane of the wave has pred set (a wave-uniform branch lets the
 // rare paths below cost nothing when no lane takes them).
 __device__ __forceinline__ bool any_lane(bool pred) {
   return __builtin_amdgcn_ballot_w64(pred) != 0;
 }
 
-// EOS: 0 = ideal gas p = e/3, 1 = bag model (compile-time, as the paper
-// specialises its kernels per EOS instead of branching at run time).
+// EOS: 0 = ideal gas p = e/3, 1 = bag model, 2 = tabled p(e), linear between
+// nodes (compile-time, as the paper specialises its kernels per EOS instead of
+// branching at run time).
 template <int EOS>
 __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
                                              double Mpar, double Mt1,
@@ -114,9 +149,29 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
   const double M2c = r.clamped ? kE2 : M2;
   double w, e;
   bool rare;
+  double ta = 0.0, tb = 0.0;   // tabled EOS: the segment's p = ta e + tb
   if constexpr (EOS == 0) {
     rare = !(Ec > 1e-140 && Ec < 1e140);
     ideal_root(Ec, M2c, w, e);
+  } else if constexpr (EOS == 2) {
+    // Tabled EOS: the recovery function v (E + p(E - M v)) - M increases
+    // with v, so the root e* lies above node e_k exactly when
+    // (E - e_k)(E + p_k) > |M|^2; the largest such k <= m-2 gives the
+    // segment (the last one continues past the last node), whose line
+    // p = a e + b gives the root in closed form.
+    const int m = eos.n;
+    const double* te = eos.tab;
+    const double* tp = eos.tab + m;
+    int k = 0;
+    for (int step = 1 << (31 - __builtin_clz(m - 1)); step > 0; step >>= 1) {
+      const int j = k + step;
+      if (j <= m - 2 && M2c < (Ec - te[j]) * (Ec + tp[j])) k = j;
+    }
+    ta = eos.tab[2 * m + k];
+    tb = eos.tab[3 * m + k];
+    rare = !(Ec > 1e-140 && Ec < 1e140);
+    linear_root(ta, tb, Ec, M2c, w, e);
+    r.p = __builtin_fma(ta, e, tb);
   } else {
     // bag model: the recovery function v (E + p(E - M v)) - M increases with
     // v, so its sign at the edges of the mixed phase selects the branch:
@@ -144,8 +199,13 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
   // clamped.
   if (any_lane(rare || r.clamped)) {
     if (rare) {
-      ideal_root_scaled(Ec, M2c, w, e);
-      r.p = e * kThird;
+      if constexpr (EOS == 2) {
+        linear_root_scaled(ta, tb, Ec, M2c, w, e);
+        r.p = __builtin_fma(ta, e, tb);
+      } else {
+        ideal_root_scaled(Ec, M2c, w, e);
+        r.p = e * kThird;
+      }
     }
     if (r.clamped) w *= kE * rcp(sqrt_pos(M2));
   }

@@ -84,6 +84,20 @@ def test_state_and_eos_validation(b):
     assert b.shasta_set_eos(h, 1, bad, 2) == b.EINVAL
     assert b.shasta_set_eos(h, 7, None, 0) == b.EINVAL
     assert b.shasta_set_eos(h, 0, None, 0) == b.OK
+    # tabled EOS: {e_0..e_m-1, p_0..p_m-1}
+    def table(vals):
+        return (ctypes.c_double * len(vals))(*vals), len(vals)
+    good = [0.0, 1.0, 2.0, 0.0, 0.3, 0.5]
+    assert b.shasta_set_eos(h, 2, *table(good)) == b.OK
+    for bad_t in ([0.0, 1.0, 0.0], [0.1, 1.0, 0.0, 0.3],          # odd n, e_0 != 0
+                  [0.0, 1.0, 1.0, 0.0, 0.3, 0.5],                  # e not increasing
+                  [0.0, 1.0, 2.0, 0.0, 1.5, 1.6],                  # slope > 1
+                  [0.0, 1.0, 2.0, 0.0, 0.3, 0.2],                  # slope < 0
+                  [0.0, 1.0, -0.1, 0.2], [0.0, float("nan"), 0.0, 0.1]):
+        assert b.shasta_set_eos(h, 2, *table(bad_t)) == b.EINVAL, bad_t
+    big = [float(k) for k in range(1025)] + [k / 3.0 for k in range(1025)]
+    assert b.shasta_set_eos(h, 2, *table(big)) == b.EINVAL           # more than 1024 nodes
+    assert b.shasta_set_eos(h, 0, None, 0) == b.OK
     assert b.shasta_set_step_index(h, -3) == b.EINVAL
     assert b.shasta_set_tiles(h, 1, 8, 16) == b.EINVAL   # segment < 16
     assert b.shasta_set_tiles(h, 2, 32, 48) == b.EINVAL  # lanes not 16/32/64

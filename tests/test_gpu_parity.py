@@ -311,6 +311,38 @@ def test_bag_eos_fp64_vs_oracle(B, torch, orc_bag):
     assert (P["e"] < e_H).any() and ((P["e"] > e_H) & (P["e"] < eQ)).any() and (P["e"] > eQ).any()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_table_eos_vs_oracle(B, torch, precision):
+    # tabled EOS (48-node crossover table): GPU closed form per segment vs the
+    # oracle's fixed point through the interpolated table
+    import oracle
+    te, tp = inputs.crossover_eos_table()
+    o = oracle.Oracle(oracle.EOS_TABLE, table=(te, tp))
+    dims = (33, 29, 27)
+    prim = inputs.hotspots(dims, 0.1, 10, seed=7, amp=(0.5, 12.0), e_bg=0.01,
+                           sigma=0.3, vz_profile=inputs.longitudinal_flow)
+    nz, ny, nx = prim.e.shape
+    s = B.Shasta([(nx, ny, nz)], 0.1, precision=precision)
+    s.set_eos_table(te, tp)
+    s.write_primitive(0, *[torch.from_numpy(a) for a in prim.as_tuple()])
+    s.step(0.04, 12)
+    got = read_np(s)
+    U = to_cons(o, prim)
+    o.run(U, 0.4, 12)
+    errs = rel_errors(got, U)
+    print("table precision", precision, "rel errors", errs)
+    assert max(errs) <= (TOL64 if precision == 0 else 2e-4)
+    # the state spans many segments of the table, below and above the crossover
+    P = o.cons_to_prim(*U)
+    segs = np.unique(np.searchsorted(te, P["e"].ravel()))
+    assert segs.size >= 15 and P["e"].max() > 2.0 and P["e"].min() < 0.1
+    # readout of the pressure goes through the same table
+    p_gpu = s.read_field(0, "p").cpu().numpy()
+    np.testing.assert_allclose(p_gpu, P["p"].reshape(p_gpu.shape),
+                               rtol=1e-11 if precision == 0 else 1e-5,
+                               atol=1e-14)
+
+
 def test_batched_equals_single_events(B, torch):
     dims = [(48, 64, 40), (24, 20, 66), (65, 33, 17)]
     prims = []
