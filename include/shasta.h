@@ -196,8 +196,9 @@ int shasta_set_antidiffusion(shasta_t* h, double diff);
 
 /* Time candidate decompositions (tiles and persistent or not) on the device
  * with the given dt, keep the fastest per axis.  A candidate's time is the
- * fastest of three blocks of reps sweeps.  The state is untouched (a sweep
- * writes only the second buffer).  Synchronous. */
+ * fastest of three blocks of reps sweeps; the four fastest of the first pass
+ * are timed again, interleaved, three more times.  The state is untouched (a
+ * sweep writes only the second buffer).  Synchronous. */
 int shasta_autotune(shasta_t* h, double dt_fm, int reps);
 
 /* Capture the steady-state step cycle (6 steps) in a HIP graph and replay it

@@ -197,6 +197,13 @@ void build_tables(shasta_t* h) {
   for (int ax = 0; ax < 3; ++ax) h->items[ax].clear();
   const int64_t total_windows = (int64_t)h->xwins.size();
   const int auto_xwin = (int)std::max<int64_t>(1, total_windows / 8192);
+  // x sweep: guided item sizes.  An item takes ceil(R / (2 * kGuideWaves))
+  // windows (R = windows not yet assigned, over all events), capped by the
+  // tuned size, so items shrink to single windows toward the end of the
+  // launch; launched largest first, the last waves are short and the GPU
+  // drains evenly.
+  const int64_t kGuideWaves = 2048;   // two waves on each of 1024 SIMDs
+  int64_t x_remaining = total_windows;
   for (int ax = 0; ax < 3; ++ax) {
     int rec = 0;
     for (int e = 0; e < ne; ++e) {
@@ -204,13 +211,19 @@ void build_tables(shasta_t* h) {
       const size_t start = h->items[ax].size();
       if (ax == 0) {
         const int64_t nwin = d.xwin_count;
-        const int per = h->xwin ? h->xwin : auto_xwin;
-        for (int64_t w = 0; w < nwin; w += per) {
+        const int cap = h->xwin ? h->xwin : auto_xwin;
+        for (int64_t w = 0; w < nwin;) {
+          const int64_t guided = (x_remaining + 2 * kGuideWaves - 1) / (2 * kGuideWaves);
+          const int64_t take = std::min<int64_t>({(int64_t)cap, std::max<int64_t>(1, guided),
+                                                  nwin - w});
           Item it{};
           it.ev = e;
           it.a = (int32_t)w;
-          it.b = (int32_t)std::min<int64_t>(per, nwin - w);
+          it.b = (int32_t)take;
+          it.rec = rec + (int32_t)(h->items[ax].size() - start);
           h->items[ax].push_back(it);
+          w += take;
+          x_remaining -= take;
         }
       } else {
         const int N = h->dims[3 * e + ax];
@@ -235,6 +248,7 @@ void build_tables(shasta_t* h) {
               it.s0 = s0;
               it.s1 = std::min(N, s0 + L);
               it.lx = lx;
+              it.rec = (int32_t)h->items[ax].size();
               h->items[ax].push_back(it);
             }
       }
@@ -244,6 +258,10 @@ void build_tables(shasta_t* h) {
       rec += d.rec_count[ax];
     }
     h->n_records[ax] = rec;
+    // x sweep: launch the largest items first (records stay per event)
+    if (ax == 0)
+      std::stable_sort(h->items[0].begin(), h->items[0].end(),
+                       [](const Item& a, const Item& b) { return a.b > b.b; });
     // queue order of a persistent launch: largest estimated work first
     std::vector<double> cost(h->items[ax].size());
     for (size_t i = 0; i < cost.size(); ++i) {
@@ -887,53 +905,72 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
     return SHASTA_OK;
   };
   int rc = SHASTA_OK;
-  // x sweep: windows per wave, queue or one wave per item
-  {
-    float best = 1e30f;
-    int best_w = h->xwin;
-    bool best_p = h->persistent[0];
-    for (int pers = 0; pers < 2 && rc == SHASTA_OK; ++pers)
-      for (int w : {1, 2, 3, 4, 6, 8, 12, 16}) {
-        h->xwin = w;
-        h->persistent[0] = pers;
-        build_tables(h);
-        if ((rc = upload_tables(h))) break;
+  // A candidate decomposition of one axis: x: windows per wave (p0); y/z:
+  // segment length (p0) and lanes along x (p1); persistent launch or not.
+  struct Cand {
+    int p0, p1;
+    bool pers;
+    float ms;
+  };
+  auto apply = [&](int ax, const Cand& c) -> int {
+    if (ax == 0) {
+      h->xwin = c.p0;
+    } else {
+      h->seg[ax] = c.p0;
+      h->lanes[ax] = c.p1;
+    }
+    h->persistent[ax] = c.pers;
+    build_tables(h);
+    return upload_tables(h);
+  };
+  for (int ax = 0; ax < 3 && rc == SHASTA_OK; ++ax) {
+    std::vector<Cand> cands;
+    for (int pers = 0; pers < 2; ++pers) {
+      if (ax == 0) {
+        for (int w : {2, 4, 6, 8, 12, 16, 24, 32}) cands.push_back({w, 0, pers != 0, 0.0f});
+      } else {
+        // segment lengths: whole pencils, pencils cut into 2..8 equal parts,
+        // and a few fixed lengths (a segment recomputes 6 cells per side)
+        std::vector<int> len;
+        for (int parts = 1; parts <= 8; ++parts) len.push_back((max_n + parts - 1) / parts);
+        for (int L : {16, 24, 32, 48, 64, 96, 128}) len.push_back(L);
+        std::sort(len.begin(), len.end());
+        len.erase(std::unique(len.begin(), len.end()), len.end());
+        for (int lx : {16, 32, 64})
+          for (int L : len)
+            if (L >= 16 || L >= max_n) cands.push_back({std::min(L, max_n), lx, pers != 0, 0.0f});
+      }
+    }
+    // first pass: every candidate once
+    for (Cand& c : cands) {
+      if ((rc = apply(ax, c))) break;
+      if ((rc = time_axis(ax, c.ms))) break;
+    }
+    if (rc) break;
+    // second pass: the four fastest again, interleaved over three rounds;
+    // a candidate keeps its fastest time
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+    const size_t top = std::min<size_t>(4, cands.size());
+    for (int round = 0; round < 3 && rc == SHASTA_OK; ++round)
+      for (size_t i = 0; i < top; ++i) {
         float ms;
-        if ((rc = time_axis(0, ms))) break;
-        if (ms < best) { best = ms; best_w = w; best_p = pers; }
+        if ((rc = apply(ax, cands[i]))) break;
+        if ((rc = time_axis(ax, ms))) break;
+        cands[i].ms = std::min(cands[i].ms, ms);
       }
-    h->xwin = best_w;
-    h->persistent[0] = best_p;
-  }
-  for (int ax = 1; ax < 3 && rc == SHASTA_OK; ++ax) {
-    float best = 1e30f;
-    int bs = h->seg[ax], bl = h->lanes[ax];
-    bool bp = h->persistent[ax];
-    // segment lengths: whole pencils, pencils cut into 2..8 equal parts, and
-    // a few fixed lengths (a segment recomputes a margin of 6 cells per side)
-    std::vector<int> cand;
-    for (int parts = 1; parts <= 8; ++parts) cand.push_back((max_n + parts - 1) / parts);
-    for (int L : {16, 24, 32, 48, 64, 96, 128}) cand.push_back(L);
-    std::sort(cand.begin(), cand.end());
-    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-    for (int pers = 0; pers < 2 && rc == SHASTA_OK; ++pers)
-      for (int lx : {16, 32, 64}) {
-        for (int L : cand) {
-          if (L < 16 && L < max_n) continue;
-          h->seg[ax] = std::min(L, max_n);
-          h->lanes[ax] = lx;
-          h->persistent[ax] = pers;
-          build_tables(h);
-          if ((rc = upload_tables(h))) break;
-          float ms;
-          if ((rc = time_axis(ax, ms))) break;
-          if (ms < best) { best = ms; bs = h->seg[ax]; bl = lx; bp = pers; }
-        }
-        if (rc) break;
-      }
-    h->seg[ax] = bs;
-    h->lanes[ax] = bl;
-    h->persistent[ax] = bp;
+    if (rc) break;
+    size_t best = 0;
+    for (size_t i = 1; i < top; ++i)
+      if (cands[i].ms < cands[best].ms) best = i;
+    Cand c = cands[best];
+    if (ax == 0) {
+      h->xwin = c.p0;
+    } else {
+      h->seg[ax] = c.p0;
+      h->lanes[ax] = c.p1;
+    }
+    h->persistent[ax] = c.pers;
   }
   build_tables(h);
   int rc2 = upload_tables(h);

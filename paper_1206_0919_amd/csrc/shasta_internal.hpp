@@ -7,7 +7,10 @@ namespace shasta {
 
 constexpr int kNF = 5;            // E, M_x, M_y, M_z, R
 constexpr int kWavesPerBlock = 4; // 256-thread blocks, each wave independent
-constexpr int kXCells = 4;        // x sweep: consecutive positions per lane
+#ifndef SHASTA_XCELLS
+#define SHASTA_XCELLS 2
+#endif
+constexpr int kXCells = SHASTA_XCELLS;  // x sweep: consecutive positions per lane
 constexpr int kXWindow = 64 * kXCells;  // positions held by one wave
 constexpr int kHalo = 6;          // halo of a row piece (two half steps of 3)
 constexpr int kMarchLag = 6;      // y/z sweep: output lags input by 6 cells
@@ -66,7 +69,9 @@ struct Item {
   int32_t s0;   // y/z: written segment [s0, s1) along the sweep axis
   int32_t s1;
   int32_t lx;   // y/z: lanes along x (16, 32, 64)
-  int32_t pad[2];
+  int32_t rec;  // reduction record of the item (records are contiguous per
+                // event, whatever order the items are launched in)
+  int32_t pad;
 };
 
 constexpr int kMaxEosNodes = 1024;   // tabled EOS: most nodes

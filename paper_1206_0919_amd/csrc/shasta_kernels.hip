@@ -12,10 +12,9 @@
 //    marches along the sweep axis through a software pipeline.  Cell i of
 //    U^n enters at iteration i; U^{n+1/2} of cell i-3 and U^{n+1} of cell i-6
 //    leave in the same iteration, so each quantity is computed once.
-//  - x sweep (sweep_x): a lane owns 4 consecutive cells of the x-fastest
-//    array; a wave covers 256 cells of the flattened grid, neighbours come
-//    from the adjacent lane through cross-lane shuffles, and the outflow halo
-//    of each row is applied cell by cell (rows may start anywhere in a wave).
+//  - x sweep (sweep_x): a lane owns kXCells (2) consecutive positions of a
+//    window of 64 kXCells positions that holds row pieces with their halos;
+//    neighbours come from the adjacent lane through cross-lane shuffles.
 //
 // Both organisations call the same arithmetic (shasta_math.hpp) with the
 // same operands, so an x sweep and a y or z sweep of transposed data agree
@@ -50,8 +49,9 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // acc[0..4] sums, [5..9] ledger, [10] max eps, [11] clamp, [12] floor.
-// One record per work item, written by lane 0: deterministic (fixed
-// butterfly) and independent of which block or wave processed the item.
+// One record per work item (at the item's record index), written by lane 0:
+// deterministic (fixed butterfly) and independent of which block or wave
+// processed the item.
 __device__ __forceinline__ void wave_record(const double (&acc)[13], double* rec, int item) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -483,7 +483,7 @@ void sweep_march(SweepArgs A) {
     __syncthreads();
     if (wave == 0 && lane == 0) {
       for (int j = 0; j < 13; ++j)
-        A.rec[(size_t)item * R_SIZE + j] = (j == R_MAXEPS) ? fmax(v[j], part[j]) : v[j] + part[j];
+        A.rec[(size_t)it.rec * R_SIZE + j] = (j == R_MAXEPS) ? fmax(v[j], part[j]) : v[j] + part[j];
       if (PERSIST) next = atomicAdd(A.counter, 1) + (int)gridDim.x;
     }
     if (!PERSIST) break;
@@ -495,7 +495,8 @@ void sweep_march(SweepArgs A) {
 }
 
 // ------------------------------------------------------------ x sweep
-// A window holds up to 256 positions, 4 consecutive ones per lane.  It covers
+// A window holds up to 64 kXCells positions, kXCells consecutive ones per lane
+// (two: 162 registers in FP64, three waves per SIMD).  It covers
 // the cells [c0, c1) of the x-fastest array as row pieces, each preceded and
 // followed by 6 halo positions whose loads are clamped to the row (outflow
 // copy), exactly as the march treats the ends of a pencil.  The stencil then
@@ -588,7 +589,7 @@ void sweep_x(SweepArgs A) {
   __shared__ T halo[kWavesPerBlock][3][kXWindow];
   // wave-uniform: lets the compiler keep the work item in scalar registers
   for (int kq = __builtin_amdgcn_readfirstlane(
-           (PERSIST ? (int)blockIdx.x : xcd_block()) * kWavesPerBlock + wave);
+           (int)blockIdx.x * kWavesPerBlock + wave);
        kq < A.n_items;) {
   const int item = __builtin_amdgcn_readfirstlane(item_at(A, kq));
   const Item it = A.items[item];
@@ -779,7 +780,7 @@ void sweep_x(SweepArgs A) {
   }
   acc[R_CLAMP] = double(n_clamp);
   acc[R_FLOOR] = double(n_floor);
-  wave_record(acc, A.rec, item);
+  wave_record(acc, A.rec, it.rec);
   if (!PERSIST) break;
   int nk = 0;
   if (lane == 0) nk = atomicAdd(A.counter, 1) + (int)gridDim.x * kWavesPerBlock;
