@@ -32,6 +32,7 @@ CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
 EOS_IDEAL = 0
 EOS_BAG = 1
 EOS_TABLE = 2
+EOS_BARYON = 3
 
 
 def build(src: str = _SRC, out: str = _LIB, extra=()) -> str:
@@ -45,7 +46,8 @@ class _Eos(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("B", ctypes.c_double),
                 ("e_H", ctypes.c_double), ("n", ctypes.c_int),
                 ("te", ctypes.POINTER(ctypes.c_double)),
-                ("tp", ctypes.POINTER(ctypes.c_double))]
+                ("tp", ctypes.POINTER(ctypes.c_double)),
+                ("cs2", ctypes.c_double), ("mass", ctypes.c_double)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -63,9 +65,9 @@ def load(path: str = _LIB):
             raise FileNotFoundError(path)
     lib = ctypes.CDLL(path)
     lib.orc_pressure.restype = ctypes.c_double
-    lib.orc_pressure.argtypes = [ctypes.POINTER(_Eos), ctypes.c_double]
+    lib.orc_pressure.argtypes = [ctypes.POINTER(_Eos), ctypes.c_double, ctypes.c_double]
     lib.orc_recover.restype = ctypes.c_int
-    lib.orc_recover.argtypes = [ctypes.POINTER(_Eos)] + [ctypes.c_double] * 4 + \
+    lib.orc_recover.argtypes = [ctypes.POINTER(_Eos)] + [ctypes.c_double] * 5 + \
         [_dp] * 6 + [ctypes.POINTER(ctypes.c_int)] * 3
     lib.orc_prim_to_cons.restype = None
     lib.orc_prim_to_cons.argtypes = [ctypes.POINTER(_Eos), ctypes.c_int64] + [_dp] * 10
@@ -99,35 +101,38 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_dp)
 
 
-def make_eos(kind: int = EOS_IDEAL, B: float = 0.0, e_H: float = 0.0, table=None):
+def make_eos(kind: int = EOS_IDEAL, B: float = 0.0, e_H: float = 0.0, table=None,
+             cs2: float = 1.0 / 3.0, mass: float = 0.0):
     """EOS descriptor; for EOS_TABLE, table = (node energy densities, node
-    pressures).  Returns (descriptor, arrays it points into)."""
+    pressures); for EOS_BARYON, p = cs2 (e - mass n).  Returns (descriptor,
+    arrays it points into)."""
     if kind == EOS_TABLE:
         te = np.ascontiguousarray(table[0], dtype=np.float64)
         tp = np.ascontiguousarray(table[1], dtype=np.float64)
         assert te.size == tp.size >= 2
-        return _Eos(int(kind), 0.0, 0.0, te.size, _ptr(te), _ptr(tp)), (te, tp)
-    return _Eos(int(kind), float(B), float(e_H), 0, None, None), ()
+        return _Eos(int(kind), 0.0, 0.0, te.size, _ptr(te), _ptr(tp), 0.0, 0.0), (te, tp)
+    return _Eos(int(kind), float(B), float(e_H), 0, None, None, float(cs2), float(mass)), ()
 
 
 class Oracle:
     """Thin ctypes front end; state lives in numpy arrays owned by the caller."""
 
-    def __init__(self, eos_kind=EOS_IDEAL, B=0.0, e_H=0.0, lib_path=_LIB, table=None):
+    def __init__(self, eos_kind=EOS_IDEAL, B=0.0, e_H=0.0, lib_path=_LIB, table=None,
+                 cs2=1.0 / 3.0, mass=0.0):
         self.lib_path = lib_path
         self.lib = load(lib_path)
-        self.eos, self._keep = make_eos(eos_kind, B, e_H, table)
+        self.eos, self._keep = make_eos(eos_kind, B, e_H, table, cs2, mass)
 
     # eq. (cf-*) and the EOS closure
-    def pressure(self, e: float) -> float:
-        return self.lib.orc_pressure(ctypes.byref(self.eos), float(e))
+    def pressure(self, e: float, n: float = 0.0) -> float:
+        return self.lib.orc_pressure(ctypes.byref(self.eos), float(e), float(n))
 
     # Sec. 3 last paragraph: fixed-point eigenframe recovery of one cell
-    def recover(self, E, Mx, My, Mz):
+    def recover(self, E, Mx, My, Mz, R=0.0):
         out = [ctypes.c_double() for _ in range(6)]
         it, cl, fl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         ok = self.lib.orc_recover(ctypes.byref(self.eos), float(E), float(Mx),
-                                  float(My), float(Mz),
+                                  float(My), float(Mz), float(R),
                                   *[ctypes.byref(o) for o in out],
                                   ctypes.byref(it), ctypes.byref(cl), ctypes.byref(fl))
         e, p, v, vx, vy, vz = (o.value for o in out)

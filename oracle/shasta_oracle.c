@@ -60,7 +60,12 @@ enum { ORC_NF = 5 };
  * kind 2: tabled EOS (Sec. 2 and Sec. 3, last paragraph: a tabulated p(e)
  * read through an interpolation, the reason the recovery is a root search):
  * nodes te[0] = 0 < te[1] < ... < te[n-1] with pressures tp[k], p(e) linear
- * between neighbouring nodes and the last segment continued beyond te[n-1]. */
+ * between neighbouring nodes and the last segment continued beyond te[n-1].
+ * kind 3: baryon-dependent EOS p(e, n) = cs2 max(0, e - mass n) (Sec. 3,
+ * last paragraph: the pressure follows from the energy density and the
+ * baryon density of the rest frame): a gas whose pressure comes from the
+ * energy above the rest-mass density mass * n, never negative; the recovery
+ * then needs n = R sqrt(1 - v^2) at every iterate. */
 typedef struct {
   int kind;
   double B;
@@ -68,10 +73,18 @@ typedef struct {
   int n;             /* kind 2: number of nodes (>= 2) */
   const double* te;  /* kind 2: node energy densities */
   const double* tp;  /* kind 2: node pressures */
+  double cs2;        /* kind 3: dp/de at fixed n */
+  double mass;       /* kind 3: rest mass per baryon [GeV] */
 } orc_eos;
 
-double orc_pressure(const orc_eos* eos, double e) {
+/* Pressure at rest-frame energy density e and baryon density nb (nb is used
+ * by kind 3 only). */
+double orc_pressure(const orc_eos* eos, double e, double nb) {
   if (eos->kind == 0) return e / 3.0;
+  if (eos->kind == 3) {
+    const double internal = e - eos->mass * nb;
+    return eos->cs2 * (internal > 0.0 ? internal : 0.0);
+  }
   if (eos->kind == 2) {
     /* segment k with te[k] <= e < te[k+1], by bisection over the nodes;
      * k = n-2 for e >= te[n-2] (the last segment, extended) */
@@ -107,7 +120,7 @@ typedef struct {
  * as M_a^2 + (M_b^2 + M_c^2): a sweep passes its parallel component first, so
  * the result does not depend on how the two transverse axes are labelled. */
 int orc_recover(const orc_eos* eos, double E, double Mx, double My, double Mz,
-                double* e_out, double* p_out, double* v_out, double* vx,
+                double R, double* e_out, double* p_out, double* v_out, double* vx,
                 double* vy, double* vz, int* iters_out, int* clamped,
                 int* floored) {
   const double M = sqrt(Mx * Mx + (My * My + Mz * Mz));
@@ -120,7 +133,8 @@ int orc_recover(const orc_eos* eos, double E, double Mx, double My, double Mz,
     v = Mc / Ec;
     for (;;) {
       const double e_trial = Ec - Mc * v;
-      const double vn = Mc / (Ec + orc_pressure(eos, e_trial));
+      const double n_trial = R * sqrt(1.0 - v * v);
+      const double vn = Mc / (Ec + orc_pressure(eos, e_trial, n_trial));
       ++it;
       const double change = fabs(vn - v);
       v = vn;
@@ -130,7 +144,7 @@ int orc_recover(const orc_eos* eos, double E, double Mx, double My, double Mz,
   }
   const double e = Ec - Mc * v;
   *e_out = e;
-  *p_out = orc_pressure(eos, e);
+  *p_out = orc_pressure(eos, e, R * sqrt(1.0 - v * v));
   *v_out = v;
   if (M > 0.0) {
     *vx = v * Mx / M;
@@ -152,7 +166,7 @@ void orc_prim_to_cons(const orc_eos* eos, int64_t ncell, const double* e,
                       const double* n, double* E, double* Mx, double* My,
                       double* Mz, double* R) {
   for (int64_t i = 0; i < ncell; ++i) {
-    const double p = orc_pressure(eos, e[i]);
+    const double p = orc_pressure(eos, e[i], n[i]);
     const double v2 = vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
     const double g2 = 1.0 / (1.0 - v2);
     const double w = (e[i] + p) * g2;
@@ -171,7 +185,7 @@ void orc_cons_to_prim(const orc_eos* eos, int64_t ncell, const double* E,
                       double* vy, double* vz, double* n) {
   for (int64_t i = 0; i < ncell; ++i) {
     double v;
-    orc_recover(eos, E[i], Mx[i], My[i], Mz[i], &e[i], &p[i], &v, &vx[i],
+    orc_recover(eos, E[i], Mx[i], My[i], Mz[i], R[i], &e[i], &p[i], &v, &vx[i],
                 &vy[i], &vz[i], NULL, NULL, NULL);
     n[i] = R[i] * sqrt(1.0 - v * v);
   }
@@ -281,7 +295,7 @@ static void orc_sweep_pencil(const orc_eos* eos, int N, int axis, double lam,
   for (int i = 0; i < n; ++i) {
     double e, p, v, vel[3];
     int it, cl, fl;
-    if (!orc_recover(eos, u[0][i], u[qpar][i], u[qt1][i], u[qt2][i], &e, &p,
+    if (!orc_recover(eos, u[0][i], u[qpar][i], u[qt1][i], u[qt2][i], u[4][i], &e, &p,
                      &v, &vel[0], &vel[1], &vel[2], &it, &cl, &fl))
       cnt->noconv++;
     cnt->clamp += cl;
@@ -301,7 +315,7 @@ static void orc_sweep_pencil(const orc_eos* eos, int N, int axis, double lam,
   for (int i = 0; i < n; ++i) {
     double e, p, v, vel[3];
     int it, cl, fl;
-    if (!orc_recover(eos, uh[0][i], uh[qpar][i], uh[qt1][i], uh[qt2][i], &e,
+    if (!orc_recover(eos, uh[0][i], uh[qpar][i], uh[qt1][i], uh[qt2][i], uh[4][i], &e,
                      &p, &v, &vel[0], &vel[1], &vel[2], &it, &cl, &fl))
       cnt->noconv++;
     cnt->clamp += cl;

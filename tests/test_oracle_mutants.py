@@ -29,7 +29,7 @@ MUTANTS = {
     "limiter_drops_term": ("fmin(fmin(s * Dh[P(j + 1)], fabs(Aph)), s * Dh[P(j - 1)])", "fmin(s * Dh[P(j + 1)], fabs(Aph))"),
     "limiter_wrong_neighbour": ("s * Dh[P(j - 1)])", "s * Dh[P(j)])"),
     "update_sign": ("Uh[P(j)] - (A[P(j)] - A[P(j - 1)])", "Uh[P(j)] - (A[P(j)] + A[P(j - 1)])"),
-    "recovery_uses_E_for_p": ("orc_pressure(eos, e_trial)", "orc_pressure(eos, Ec)"),
+    "recovery_uses_E_for_p": ("orc_pressure(eos, e_trial, n_trial)", "orc_pressure(eos, Ec, n_trial)"),
     "recovery_loose_tolerance": ("1125899906842624.0", "1048576.0"),
     "predictor_full_lambda_velocity": ("eps[i] = (0.5 * lam) * vel[0];", "eps[i] = lam * vel[0];"),
     "predictor_full_lambda_source": ("src, 0.5 * lam, diff, uh[q] + ORC_HALO", "src, lam, diff, uh[q] + ORC_HALO"),
@@ -42,6 +42,10 @@ MUTANTS = {
     "energy_definition": ("E[i] = (e[i] + p * v2) * g2;", "E[i] = (e[i] + p) * g2;"),
     "velocity_direction": ("*vy = v * My / M;", "*vy = v * Mx / M;"),
     "bag_mixed_phase": ("if (e < e_Q) return eos->e_H / 3.0;", "if (e < e_Q) return e / 3.0;"),
+    "baryon_density_not_contracted": ("const double n_trial = R * sqrt(1.0 - v * v);",
+                                      "const double n_trial = R;"),
+    "baryon_mass_sign": ("const double internal = e - eos->mass * nb;",
+                         "const double internal = e + eos->mass * nb;"),
     "table_wrong_anchor": ("return eos->tp[k] + slope * (e - eos->te[k]);",
                            "return eos->tp[k] + slope * (e - eos->te[k + 1]);"),
     "table_search_off_by_one": ("if (eos->te[mid] <= e) lo = mid; else hi = mid;",
@@ -52,6 +56,7 @@ PINS = [
     lambda o, ob: tr.test_recovery_ideal_closed_form(o),
     lambda o, ob: tr.test_recovery_bag_closed_form(ob),
     lambda o, ob: tr.test_prim_cons_round_trip(o),
+    lambda o, ob: tr.check_baryon_round_trip(tr._baryon_oracle(lib_path=o.lib_path)),
     lambda o, ob: tr.check_table_closed_form(
         oracle.Oracle(oracle.EOS_TABLE, table=inputs.crossover_eos_table(), lib_path=o.lib_path)),
     lambda o, ob: tf.test_phoenical_identity_at_rest(o),

@@ -153,6 +153,85 @@ def test_table_through_bag_break_points_is_the_bag_model(orc_bag):
         assert a["p"] == pytest.approx(b["p"], rel=1e-14, abs=1e-15 * Ei)
 
 
+M_N = 0.938   # nucleon mass [GeV]
+
+
+def _baryon_oracle(cs2=1.0 / 3.0, mass=M_N, lib_path=None):
+    import oracle
+    kw = {} if lib_path is None else dict(lib_path=lib_path)
+    return oracle.Oracle(oracle.EOS_BARYON, cs2=cs2, mass=mass, **kw)
+
+
+def test_baryon_eos_without_mass_is_linear(orc):
+    # mass = 0: p = cs2 e, the closed form of a linear branch
+    for cs2 in (1.0 / 3.0, 0.2):
+        o = _baryon_oracle(cs2, 0.0)
+        E, r, d = _samples(21, 200)
+        for Ei, ri, di in zip(E, r, d):
+            M = ri * Ei
+            res = o.recover(Ei, *(M * di), R=0.3 * Ei)
+            v_ex, e_ex = closed_form_v(Ei, M, [(cs2, 0.0, -np.inf, np.inf)])
+            assert abs(res["v"] - v_ex) <= 4e-15 * max(v_ex, 1e-300) + 1e-300
+
+
+def check_baryon_round_trip(o, cs2=1.0 / 3.0, mass=M_N):
+    # primitives -> conserved by eqs. cf-density, cf-momentum, cf-energy
+    # (written out here), then the recovery must return the primitives:
+    # e, n = R sqrt(1 - v^2) and v
+    rng = np.random.default_rng(22)
+    for _ in range(400):
+        e = 10 ** rng.uniform(-3, 2)
+        n = rng.uniform(0.0, 0.9) * e / mass        # internal energy e - m n >= 0
+        v = rng.uniform(0.0, 0.98)
+        p = cs2 * (e - mass * n)
+        g2 = 1.0 / (1.0 - v * v)
+        E = (e + p) * g2 - p
+        M = (e + p) * g2 * v
+        R = n * math.sqrt(g2)
+        res = o.recover(E, 0.0, 0.0, M, R=R)
+        assert res["converged"]
+        assert res["v"] == pytest.approx(v, rel=1e-12, abs=1e-14)
+        assert res["e"] == pytest.approx(e, rel=1e-11)
+        assert res["p"] == pytest.approx(p, rel=1e-10, abs=1e-14 * e)
+
+
+def test_baryon_eos_round_trip():
+    check_baryon_round_trip(_baryon_oracle())
+
+
+def test_baryon_eos_never_negative_pressure():
+    # a state with more rest mass than energy: p = 0, the recovery stays finite
+    o = _baryon_oracle()
+    res = o.recover(1.0, 0.6, 0.0, 0.0, R=5.0)
+    assert res["converged"] and res["p"] == 0.0 and 0.0 < res["v"] < 1.0
+    assert res["v"] == pytest.approx(0.6, rel=1e-15)     # v = M / (E + 0)
+
+
+def test_baryon_eos_bisection():
+    # the root of v (E + p(E - M v, R sqrt(1 - v^2))) - M = 0 by bisection
+    cs2, mass = 1.0 / 3.0, M_N
+    o = _baryon_oracle(cs2, mass)
+    rng = np.random.default_rng(23)
+    for _ in range(200):
+        # a state from valid primitives (e >= mass n), as the scheme evolves
+        e0 = 10 ** rng.uniform(-2, 2)
+        n0 = rng.uniform(0.0, 0.9) * e0 / mass
+        v0 = rng.uniform(0.0, 0.98)
+        p0 = cs2 * (e0 - mass * n0)
+        g2 = 1.0 / (1.0 - v0 * v0)
+        E, M, R = (e0 + p0) * g2 - p0, (e0 + p0) * g2 * v0, n0 * math.sqrt(g2)
+
+        def f(v):
+            internal = (E - M * v) - mass * R * math.sqrt(1 - v * v)
+            return v * (E + cs2 * max(internal, 0.0)) - M
+        lo, hi = 0.0, 1.0 - 1e-16
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if f(mid) < 0 else (lo, mid)
+        res = o.recover(E, M, 0.0, 0.0, R=R)
+        assert res["v"] == pytest.approx(0.5 * (lo + hi), rel=4e-15, abs=1e-15)
+
+
 def test_guard_clamp_and_floor(orc):
     # |M| >= E: clamped to (1 - 1e-10) E, direction kept, counted
     res = orc.recover(1.0, 2.0, 0.0, 0.0)
