@@ -55,6 +55,7 @@ typedef struct shasta_handle shasta_t;
 #define SHASTA_EOS_BAG 1   /* bag model: p = e/3 (e <= e_H), e_H/3 in the
                               mixed phase, (e - 4B)/3 (e >= e_H + 4B)        */
 #define SHASTA_EOS_TABLE 2 /* tabulated p(e), linear between nodes          */
+#define SHASTA_EOS_BARYON 3 /* p(e, n) = cs2 max(0, e - mass n)             */
 
 /* field indices for shasta_read_field */
 #define SHASTA_FIELD_E 0
@@ -101,8 +102,13 @@ int shasta_bind_workspace(shasta_t* h, void* dev_ptr, size_t bytes);
  * 2 <= m <= 1024, host memory, copied: e_0 = 0 < e_1 < ... (GeV/fm^3),
  * p_k >= 0, finite, every slope (p_{k+1} - p_k)/(e_{k+1} - e_k) in [0, 1];
  * p is linear between neighbouring nodes and the last segment continues
- * past e_{m-1}.  EINVAL on any violation (the previous EOS stays).  May be
- * called before or after shasta_bind_workspace. */
+ * past e_{m-1}.  SHASTA_EOS_BARYON (the pressure from the rest-frame energy
+ * and baryon densities, Sec. 3, last paragraph) takes params = {cs2, mass}:
+ * p = cs2 max(0, e - mass n), 0 < cs2 <= 1, mass >= 0 in GeV; its recovery
+ * solves for v with n = R sqrt(1 - v^2) (safeguarded Newton iteration).
+ * EINVAL on any violation (the previous EOS stays).  May be called before or
+ * after shasta_bind_workspace.  The tabled and baryon EOS always use the grid
+ * launch (shasta_set_persistent is then ignored). */
 int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params);
 
 /* Write the state of event ev from primitive fields (device pointers to
@@ -225,6 +231,14 @@ int shasta_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
  * kernels.  Synchronous. */
 int shasta_selftest_math(const double* in_dev, double* out_dev, int n,
                          int which, void* hip_stream);
+
+/* Recovery self-check with the handle's EOS (Sec. 3, last paragraph: the
+ * boost to the rest frame): for n cells, in_dev[5i..5i+4] = (E, M_x, M_y,
+ * M_z, R) -> out_dev[4i..4i+3] = (e, p, |v|, clamped + 2 floored), computed
+ * by the same device code the sweeps use.  Device pointers; needs a bound
+ * workspace (the tabled EOS lives there); synchronous on the handle's
+ * stream. */
+int shasta_selftest_recover(shasta_t* h, const double* in_dev, double* out_dev, int n);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("SHASTA_LIB") or os.path.join(HERE, "lib", "libshasta.
 OK, EINVAL, ESTATE, EWORKSPACE, EHIP, ENONFINITE, ENOCONVERGE = range(7)
 FP64, FP32_MIXED = 0, 1
 BC_OUTFLOW = 0
-EOS_IDEAL, EOS_BAG, EOS_TABLE = 0, 1, 2
+EOS_IDEAL, EOS_BAG, EOS_TABLE, EOS_BARYON = 0, 1, 2, 3
 FIELDS = ("E", "Mx", "My", "Mz", "R", "e", "p", "vx", "vy", "vz", "n")
 
 if not os.path.exists(LIB_PATH):
@@ -59,6 +59,7 @@ _SIGS = {
     "shasta_read_profile": ([_h, _dp, _i64p], ctypes.c_int),
     "shasta_stream_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "shasta_selftest_math": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp], ctypes.c_int),
+    "shasta_selftest_recover": ([_h, _vp, _vp, ctypes.c_int], ctypes.c_int),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -217,6 +218,16 @@ class Shasta:
 
     def set_antidiffusion(self, diff):
         _check(self.h, shasta_set_antidiffusion(self.h, float(diff)))
+
+    def selftest_recover(self, cells):
+        """cells: (n, 5) float64 tensor of (E, Mx, My, Mz, R) -> (n, 4) tensor of
+        (e, p, |v|, clamped + 2 floored) from the device recovery."""
+        t = self.torch
+        c = cells.to(device=self.device, dtype=t.float64).contiguous()
+        out = t.empty((c.shape[0], 4), dtype=t.float64, device=self.device)
+        _check(self.h, shasta_selftest_recover(self.h, _vp(c.data_ptr()), _vp(out.data_ptr()),
+                                               c.shape[0]))
+        return out
 
     def set_graph(self, enable):
         _check(self.h, shasta_set_graph(self.h, int(bool(enable))))

@@ -33,6 +33,8 @@ hipError_t read(int fp32, EosParams eos, const void* in, int64_t pitch, int64_t 
 hipError_t zero(double* p, int64_t n, hipStream_t st);
 hipError_t copy(const void* s, void* d, size_t bytes, hipStream_t st);
 hipError_t selftest(const double* in, double* out, int n, int which, hipStream_t st);
+hipError_t selftest_recover(EosParams eos, const double* in, double* out, int n,
+                            hipStream_t st);
 hipError_t sums(int fp32, const void* in, int64_t pitch, int64_t ncell, double* scratch,
                 double* out, hipStream_t st);
 int sum_scratch_doubles();
@@ -60,7 +62,7 @@ struct shasta_handle {
   int precision = 0;
   int bc = 0;
   hipStream_t stream = nullptr;
-  EosParams eos{0, 0, 0.0, 0.0, nullptr};
+  EosParams eos{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr};
   std::vector<double> eos_tab;   // tabled EOS: the 4 m doubles of EosParams::tab
   double diff = 1.0;
 
@@ -454,8 +456,9 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
   if (a.n_items == 0) return SHASTA_OK;
   const int per_block = (axis == 0) ? kWavesPerBlock : 1;
   int grid = (a.n_items + per_block - 1) / per_block;
-  // the kernels without antiflux exist for the grid launch only
-  if (h->persistent[axis] && !a.no_antiflux) {
+  // the kernels without antiflux and those of the tabled and baryon EOS
+  // exist for the grid launch only
+  if (h->persistent[axis] && !a.no_antiflux && h->eos.kind <= SHASTA_EOS_BAG) {
     const int res = shasta_launch::resident(h->precision == SHASTA_FP32_MIXED, h->eos.kind, axis);
     if (res > 0 && res < grid) {
       grid = res;
@@ -636,13 +639,13 @@ int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params) {
   if (!h) return SHASTA_EINVAL;
   if (kind == SHASTA_EOS_IDEAL) {
     if (n_params != 0) return fail(h, SHASTA_EINVAL, "ideal EOS takes no parameters");
-    h->eos = EosParams{0, 0, 0.0, 0.0, nullptr};
+    h->eos = EosParams{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr};
   } else if (kind == SHASTA_EOS_BAG) {
     if (n_params != 2 || !params) return fail(h, SHASTA_EINVAL, "bag EOS takes {B, e_H}");
     const double B = params[0], eH = params[1];
     if (!(B > 0.0) || !(eH > 0.0) || !std::isfinite(B) || !std::isfinite(eH))
       return fail(h, SHASTA_EINVAL, "bag EOS needs B > 0 and e_H > 0");
-    h->eos = EosParams{1, 0, B, eH, nullptr};
+    h->eos = EosParams{1, 0, B, eH, 0.0, 0.0, nullptr};
   } else if (kind == SHASTA_EOS_TABLE) {
     if (!params || n_params < 4 || n_params % 2 || n_params / 2 > kMaxEosNodes)
       return fail(h, SHASTA_EINVAL, "tabled EOS takes {e_0..e_m-1, p_0..p_m-1}, 2 <= m <= " +
@@ -670,8 +673,14 @@ int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params) {
     tab[3 * m - 1] = tab[3 * m - 2];   // the last segment continues past the last node
     tab[4 * m - 1] = tab[4 * m - 2];
     h->eos_tab.swap(tab);
-    h->eos = EosParams{2, m, 0.0, 0.0, nullptr};
+    h->eos = EosParams{2, m, 0.0, 0.0, 0.0, 0.0, nullptr};
     if (int rc = upload_eos(h)) return rc;
+  } else if (kind == SHASTA_EOS_BARYON) {
+    if (n_params != 2 || !params) return fail(h, SHASTA_EINVAL, "baryon EOS takes {cs2, mass}");
+    const double cs2 = params[0], mass = params[1];
+    if (!(cs2 > 0.0 && cs2 <= 1.0) || !(mass >= 0.0) || !std::isfinite(mass))
+      return fail(h, SHASTA_EINVAL, "baryon EOS needs 0 < cs2 <= 1 and a finite mass >= 0");
+    h->eos = EosParams{3, 0, 0.0, 0.0, cs2, mass, nullptr};
   } else {
     return fail(h, SHASTA_EINVAL, "unknown EOS kind");
   }
@@ -1036,6 +1045,16 @@ int shasta_selftest_math(const double* in, double* out, int n, int which, void* 
   if (n == 0) return SHASTA_OK;
   if (shasta_launch::selftest(in, out, n, which, st) != hipSuccess) return SHASTA_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return SHASTA_EHIP;
+  return SHASTA_OK;
+}
+
+int shasta_selftest_recover(shasta_t* h, const double* in, double* out, int n) {
+  if (!h) return SHASTA_EINVAL;
+  if (!in || !out || n < 0) return fail(h, SHASTA_EINVAL, "null buffer or n < 0");
+  if (!h->ws) return fail(h, SHASTA_ESTATE, "no workspace bound");
+  if (n == 0) return SHASTA_OK;
+  HIPCHECK(h, shasta_launch::selftest_recover(h->eos, in, out, n, h->stream));
+  HIPCHECK(h, hipStreamSynchronize(h->stream));
   return SHASTA_OK;
 }
 

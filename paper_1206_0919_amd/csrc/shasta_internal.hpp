@@ -77,10 +77,12 @@ struct Item {
 constexpr int kMaxEosNodes = 1024;   // tabled EOS: most nodes
 
 struct EosParams {
-  int32_t kind;  // 0 ideal, 1 bag, 2 table
+  int32_t kind;  // 0 ideal, 1 bag, 2 table, 3 baryon-dependent
   int32_t n;     // table: nodes m
-  double B;
-  double e_H;
+  double B;      // bag: bag constant
+  double e_H;    // bag: hadron edge of the mixed phase
+  double cs2;    // baryon: p = cs2 max(0, e - mass n)
+  double mass;   // baryon: rest mass per baryon
   // table: 4 m doubles in device memory: node e_k (m), node p_k (m), and the
   // slope a_k and intercept b_k of segment k = [e_k, e_k+1] (p = a e + b;
   // entry m-1 repeats segment m-2, which continues past the last node)

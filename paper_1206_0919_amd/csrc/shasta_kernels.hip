@@ -199,7 +199,8 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
     for (int q = 0; q < kNF; ++q) L.un[uslot][q][this->lane] = u[q][S0];
     {
       const Recovered r = recover<eos_of<EOS>>(*this->eos, double(u[0][S0]), double(u[QP][S0]),
-                                       double(u[QT1][S0]), double(u[QT2][S0]));
+                                       double(u[QT1][S0]), double(u[QT2][S0]),
+                                       double(u[4][S0]));
       const double v = r.w * double(u[QP][S0]);
       ep[S0] = T(this->lamh * v);
       fE[S0] = T(r.p * v);
@@ -272,7 +273,7 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       ec[S3] = ec[S4]; fE[S3] = fE[S4]; fM[S3] = fM[S4];
     } else {
       const Recovered r = recover<eos_of<EOS>>(*this->eos, double(uh[0]), double(uh[QP]),
-                                       double(uh[QT1]), double(uh[QT2]));
+                                       double(uh[QT1]), double(uh[QT2]), double(uh[4]));
       const double v = r.w * double(uh[QP]);
       ec[S3] = T(this->lam * v);
       fE[S3] = T(r.p * v);
@@ -673,7 +674,8 @@ void sweep_x(SweepArgs A) {
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
         const Recovered r = recover<eos_of<EOS>>(A.eos, double(u[0][j]), double(u[QP][j]),
-                                         double(u[QT1][j]), double(u[QT2][j]));
+                                         double(u[QT1][j]), double(u[QT2][j]),
+                                         double(u[4][j]));
         const double v = r.w * double(u[QP][j]);
         ep[j] = T(lamh * v);
         fE[j] = T(r.p * v);
@@ -712,7 +714,8 @@ void sweep_x(SweepArgs A) {
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
         const Recovered r = recover<eos_of<EOS>>(A.eos, double(uh[0][j]), double(uh[QP][j]),
-                                         double(uh[QT1][j]), double(uh[QT2][j]));
+                                         double(uh[QT1][j]), double(uh[QT2][j]),
+                                         double(uh[4][j]));
         const double v = r.w * double(uh[QP][j]);
         ec[j] = T(lam * v);
         fEc[j] = T(r.p * v);
@@ -917,6 +920,8 @@ __global__ void prim_to_cons(EosParams eos, const double* e, const double* vx,
       p = ei * kThird;
     } else if (eos.kind == 2) {
       p = table_pressure(eos, ei);
+    } else if (eos.kind == 3) {
+      p = eos.cs2 * fmax(ei - eos.mass * ni, 0.0);
     } else {
       const double eQ = eos.e_H + 4.0 * eos.B;
       p = (ei <= eos.e_H) ? ei * kThird
@@ -959,9 +964,10 @@ __global__ void read_out(EosParams eos, const T* in, int64_t pitch, int64_t ncel
     }
     const double E = in[i], Mx = in[pitch + i], My = in[2 * pitch + i],
                  Mz = in[3 * pitch + i], R = in[4 * pitch + i];
-    const Recovered r = (eos.kind == 0)   ? recover<0>(eos, E, Mx, My, Mz)
-                        : (eos.kind == 1) ? recover<1>(eos, E, Mx, My, Mz)
-                                          : recover<2>(eos, E, Mx, My, Mz);
+    const Recovered r = (eos.kind == 0)   ? recover<0>(eos, E, Mx, My, Mz, R)
+                        : (eos.kind == 1) ? recover<1>(eos, E, Mx, My, Mz, R)
+                        : (eos.kind == 2) ? recover<2>(eos, E, Mx, My, Mz, R)
+                                          : recover<3>(eos, E, Mx, My, Mz, R);
     double out;
     switch (field) {
       case 5: out = r.e; break;
@@ -1020,6 +1026,22 @@ __global__ void stream_copy_kernel(const float4* __restrict__ s, float4* __restr
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     d[i] = s[i];
+}
+
+// Recovery self-check: cell i of in = (E, M_x, M_y, M_z, R) -> out =
+// (e, p, |v|, clamped + 2 floored), through the same recover<EOS>() the
+// sweeps call (|M|^2 summed as M_x^2 + (M_y^2 + M_z^2)).
+template <int EOS>
+__global__ void recover_selftest(EosParams eos, const double* in, double* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* c = in + 5 * (size_t)i;
+  const Recovered r = recover<EOS>(eos, c[0], c[1], c[2], c[3], c[4]);
+  double* o = out + 4 * (size_t)i;
+  o[0] = r.e;
+  o[1] = r.p;
+  o[2] = r.w * sqrt_pos(fmax(r.M2, 1e-300));
+  o[3] = double(r.clamped + 2 * r.floored);
 }
 
 __global__ void selftest_kernel(const double* in, double* out, int n, int which) {
@@ -1083,21 +1105,25 @@ hipError_t sweep_scheme_grid(int fp32, int axis, const SweepArgs& a, int grid, h
 hipError_t sweep(int fp32, int axis, const void* args, int grid, hipStream_t st) {
   const SweepArgs& a = *static_cast<const SweepArgs*>(args);
   const bool p = a.counter != nullptr;
-  if (a.no_antiflux) {
-    // grid launch only (the host never sets a queue for these kernels)
+  // The kernels without antiflux and those of the tabled and baryon EOS
+  // exist for the grid launch only (the host never sets a queue for them).
+  if (a.no_antiflux || a.eos.kind >= 2) {
     if (p) return hipErrorInvalidValue;
     constexpr int N = kNoAntiflux;
-    switch (a.eos.kind) {
-      case 0: return sweep_scheme_grid<N | 0>(fp32, axis, a, grid, st);
-      case 1: return sweep_scheme_grid<N | 1>(fp32, axis, a, grid, st);
-      case 2: return sweep_scheme_grid<N | 2>(fp32, axis, a, grid, st);
+    const int scheme = a.eos.kind | (a.no_antiflux ? N : 0);
+    switch (scheme) {
+      case N | 0: return sweep_scheme_grid<N | 0>(fp32, axis, a, grid, st);
+      case N | 1: return sweep_scheme_grid<N | 1>(fp32, axis, a, grid, st);
+      case N | 2: return sweep_scheme_grid<N | 2>(fp32, axis, a, grid, st);
+      case N | 3: return sweep_scheme_grid<N | 3>(fp32, axis, a, grid, st);
+      case 2: return sweep_scheme_grid<2>(fp32, axis, a, grid, st);
+      case 3: return sweep_scheme_grid<3>(fp32, axis, a, grid, st);
       default: return hipErrorInvalidValue;
     }
   }
   switch (a.eos.kind) {
     case 0: return sweep_scheme<0>(fp32, axis, a, grid, p, st);
     case 1: return sweep_scheme<1>(fp32, axis, a, grid, p, st);
-    case 2: return sweep_scheme<2>(fp32, axis, a, grid, p, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1106,7 +1132,6 @@ int resident(int fp32, int eos_kind, int axis) {
   switch (eos_kind) {
     case 0: return fp32 ? resident_blocks<float, 0>(axis) : resident_blocks<double, 0>(axis);
     case 1: return fp32 ? resident_blocks<float, 1>(axis) : resident_blocks<double, 1>(axis);
-    case 2: return fp32 ? resident_blocks<float, 2>(axis) : resident_blocks<double, 2>(axis);
     default: return 0;
   }
 }
@@ -1180,6 +1205,19 @@ hipError_t copy(const void* s, void* d, size_t bytes, hipStream_t st) {
   if (b < 1) b = 1;
   hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)b), dim3(256), 0, st,
                      (const float4*)s, (float4*)d, n);
+  return hipGetLastError();
+}
+
+hipError_t selftest_recover(EosParams eos, const double* in, double* out, int n,
+                            hipStream_t st) {
+  const dim3 g((n + 127) / 128), b(128);
+  switch (eos.kind) {
+    case 0: hipLaunchKernelGGL(recover_selftest<0>, g, b, 0, st, eos, in, out, n); break;
+    case 1: hipLaunchKernelGGL(recover_selftest<1>, g, b, 0, st, eos, in, out, n); break;
+    case 2: hipLaunchKernelGGL(recover_selftest<2>, g, b, 0, st, eos, in, out, n); break;
+    case 3: hipLaunchKernelGGL(recover_selftest<3>, g, b, 0, st, eos, in, out, n); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

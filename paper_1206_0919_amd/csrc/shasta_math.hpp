@@ -47,6 +47,12 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return g;
 }
 
+// True if any lane of the wave has pred set (a wave-uniform branch lets the
+// rare paths below cost nothing when no lane takes them).
+__device__ __forceinline__ bool any_lane(bool pred) {
+  return __builtin_amdgcn_ballot_w64(pred) != 0;
+}
+
 // -------------------------------------------------------------------- EOS
 // Recovery of the rest frame (Sec. 3, last paragraph).  For an EOS that is
 // linear on a branch, p = a e + b, the condition v (E + p(E - M v)) = M is a
@@ -110,6 +116,62 @@ __device__ __forceinline__ void linear_root_scaled(double a, double b, double E,
   e = __builtin_ldexp(es, k);
 }
 
+// Baryon-dependent EOS p = a max(0, e - m n) with n = R sqrt(1 - v^2) (the
+// rest-frame baryon density): the recovery condition f(v) = v (E + p) - |M|
+// = 0 has no closed form.  f increases with v; its root is |M|/E (a
+// pressureless state) exactly when x = e - m n <= 0 there, else it lies on
+// the smooth branch p = a x, inside [v0, |M|/E] with v0 the root without rest
+// mass (a lower bound: the rest mass lowers p).  The smooth branch is solved
+// by Newton's method, safeguarded by bisection of that bracket.  f is
+// homogeneous in (E, |M|, m R), so the solve runs on inputs scaled by a power
+// of two.  A lane keeps its first iterate whose step (or bracket) is at most
+// 4 ulp, so its result does not depend on the other lanes of the wave (at
+// most 9 iterations on random states).  mR = m R.
+constexpr int kNewtonMax = 16;
+
+__device__ __forceinline__ void baryon_root(double a, double mR, double E, double M2,
+                                            double& w, double& e, double& p) {
+  const int k = __builtin_amdgcn_frexp_exp(E);
+  const double Es = __builtin_ldexp(E, -k);
+  const double M2s = __builtin_ldexp(M2, -2 * k);
+  const double mRs = __builtin_ldexp(mR, -k);
+  const bool moving = M2s > 0.0;
+  const double Ms = moving ? sqrt_pos(M2s) : 0.0;
+  const double vd = Ms * rcp(Es);   // the pressureless root
+  const double xd =
+      __builtin_fma(-mRs, sqrt_pos(__builtin_fma(-vd, vd, 1.0)), __builtin_fma(-Ms, vd, Es));
+  double w0, e0;
+  linear_root(a, 0.0, Es, M2s, w0, e0);
+  double v = (xd > 0.0) ? Ms * w0 : vd;
+  double lo = v, hi = vd;
+  bool done = !moving || !(xd > 0.0);
+  for (int it = 0; it < kNewtonMax; ++it) {
+    if (!any_lane(!done)) break;
+    const double s = sqrt_pos(__builtin_fma(-v, v, 1.0));
+    const double x = __builtin_fma(-mRs, s, __builtin_fma(-Ms, v, Es));
+    const double pv = a * x;
+    const double f = __builtin_fma(v, Es + pv, -Ms);
+    const double dp = a * __builtin_fma(mRs * v, rcp(s), -Ms);
+    const double df = __builtin_fma(v, dp, Es + pv);
+    lo = (f < 0.0) ? v : lo;
+    hi = (f < 0.0) ? hi : v;
+    // Newton step if it stays in the closed bracket (at an exact root f = 0
+    // and the step is 0), else bisection; done when the step or the bracket
+    // is at most 4 ulp
+    double vn = __builtin_fma(-f, rcp(df), v);
+    vn = (vn >= lo && vn <= hi) ? vn : 0.5 * (lo + hi);
+    const double tol = 8.8817841970012523e-16 * v;   // 4 ulp
+    const bool conv = fabs(vn - v) <= tol || hi - lo <= tol;
+    v = done ? v : vn;
+    done = done || conv;
+  }
+  const double s = sqrt_pos(__builtin_fma(-v, v, 1.0));
+  const double es = __builtin_fma(-Ms, v, Es);
+  e = __builtin_ldexp(es, k);
+  p = __builtin_ldexp(a * fmax(__builtin_fma(-mRs, s, es), 0.0), k);
+  w = moving ? __builtin_ldexp(v * rcp(Ms), -k) : 0.0;
+}
+
 // Tabled EOS: segment of node e_k that holds e (largest k <= m-2 with
 // e_k <= e), by a search with the same trip count in every lane.
 __device__ __forceinline__ int table_segment_of_e(const EosParams& eos, double e) {
@@ -124,19 +186,15 @@ __device__ __forceinline__ double table_pressure(const EosParams& eos, double e)
   return __builtin_fma(eos.tab[2 * eos.n + k], e, eos.tab[3 * eos.n + k]);
 }
 
-// True if any lane of the wave has pred set (a wave-uniform branch lets the
-// rare paths below cost nothing when no lane takes them).
-__device__ __forceinline__ bool any_lane(bool pred) {
-  return __builtin_amdgcn_ballot_w64(pred) != 0;
-}
 
 // EOS: 0 = ideal gas p = e/3, 1 = bag model, 2 = tabled p(e), linear between
-// nodes (compile-time, as the paper specialises its kernels per EOS instead of
-// branching at run time).
+// nodes, 3 = baryon-dependent p(e, n) (compile-time, as the paper specialises
+// its kernels per EOS instead of branching at run time).  R, the fifth
+// conserved field, is used by EOS 3 only.
 template <int EOS>
 __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
                                              double Mpar, double Mt1,
-                                             double Mt2) {
+                                             double Mt2, double R) {
   Recovered r;
   const double t = Mt1 * Mt1 + Mt2 * Mt2;
   const double M2 = __builtin_fma(Mpar, Mpar, t);
@@ -153,6 +211,9 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
   if constexpr (EOS == 0) {
     rare = !(Ec > 1e-140 && Ec < 1e140);
     ideal_root(Ec, M2c, w, e);
+  } else if constexpr (EOS == 3) {
+    rare = false;   // the solve is scaled by construction
+    baryon_root(eos.cs2, eos.mass * R, Ec, M2c, w, e, r.p);
   } else if constexpr (EOS == 2) {
     // Tabled EOS: the recovery function v (E + p(E - M v)) - M increases
     // with v, so the root e* lies above node e_k exactly when

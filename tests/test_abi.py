@@ -95,6 +95,10 @@ def test_state_and_eos_validation(b):
                   [0.0, 1.0, 2.0, 0.0, 0.3, 0.2],                  # slope < 0
                   [0.0, 1.0, -0.1, 0.2], [0.0, float("nan"), 0.0, 0.1]):
         assert b.shasta_set_eos(h, 2, *table(bad_t)) == b.EINVAL, bad_t
+    # baryon-dependent EOS: {cs2, mass}
+    for bad_b in ([0.0, 0.9], [1.2, 0.9], [0.3, -1.0], [0.3, float("inf")], [0.3]):
+        assert b.shasta_set_eos(h, 3, *table(bad_b)) == b.EINVAL, bad_b
+    assert b.shasta_set_eos(h, 3, *table([1.0 / 3.0, 0.938])) == b.OK
     big = [float(k) for k in range(1025)] + [k / 3.0 for k in range(1025)]
     assert b.shasta_set_eos(h, 2, *table(big)) == b.EINVAL           # more than 1024 nodes
     assert b.shasta_set_eos(h, 0, None, 0) == b.OK

@@ -76,6 +76,52 @@ def test_device_math(B, torch):
     assert np.all(np.abs(got - ref) <= np.spacing(ref))
 
 
+def _eos_cases(B):
+    import oracle
+    Bc, e_H = inputs.bag_parameters()
+    te, tp = inputs.crossover_eos_table()
+    return {
+        "ideal": (oracle.Oracle(), None),
+        "bag": (oracle.Oracle(oracle.EOS_BAG, Bc, e_H), (B.EOS_BAG, (Bc, e_H))),
+        "table": (oracle.Oracle(oracle.EOS_TABLE, table=(te, tp)),
+                  (B.EOS_TABLE, list(te) + list(tp))),
+        "baryon": (oracle.Oracle(oracle.EOS_BARYON, cs2=1 / 3, mass=0.938),
+                   (B.EOS_BARYON, (1 / 3, 0.938))),
+    }
+
+
+@pytest.mark.parametrize("kind", ["ideal", "bag", "table", "baryon"])
+def test_device_recovery_vs_oracle(B, torch, kind):
+    # the recovery the sweeps call, cell by cell, against the oracle's fixed
+    # point, on states from random primitives (e over 5 decades, |v| < 0.99)
+    o, eos = _eos_cases(B)[kind]
+    rng = np.random.default_rng(31)
+    n_ = 4000
+    e = 10 ** rng.uniform(-3, 2.5, n_)
+    v = rng.uniform(0, 0.99, n_) ** 0.5 * 0.99
+    d = rng.normal(size=(3, n_))
+    d /= np.linalg.norm(d, axis=0)
+    # baryon EOS: m n from 0 to 2 e, so half of the states are pressureless
+    n = rng.uniform(0, 2.0, n_) * e / 0.938 if kind == "baryon" else 0.15 * e
+    prim = inputs.Primitive(e, v * d[0], v * d[1], v * d[2], n)
+    U = o.prim_to_cons(*prim.as_tuple())
+    s = B.Shasta([(4, 4, 4)], 0.1, eos=eos)
+    got = s.selftest_recover(torch.from_numpy(np.stack(U, axis=1))).cpu().numpy()
+    P = o.cons_to_prim(*U)
+    vref = np.sqrt(P["vx"] ** 2 + P["vy"] ** 2 + P["vz"] ** 2)
+    # p is measured against the size of its terms: near m n = e (baryon EOS)
+    # it is a small difference of two large numbers
+    for name, col, ref, scale in (("e", 0, P["e"], np.abs(P["e"])),
+                                  ("p", 1, P["p"], np.maximum(np.abs(P["p"]), P["e"] / 3)),
+                                  ("v", 2, vref, vref)):
+        rel = np.abs(got[:, col] - ref) / np.maximum(scale, 1e-300)
+        worst = int(np.argmax(rel))
+        print(kind, name, "max rel", rel.max(), "at", [U[q][worst] for q in range(5)],
+              got[worst], ref[worst])
+        assert rel.max() <= 1e-13, name
+    assert np.all(got[:, 3] == 0)
+
+
 def test_shock_tube_64_fp64_vs_oracle(B, torch, orc):
     # 64^3 planar Riemann problem, 100 steps (t = 8 fm/c).  The oracle runs on
     # 64 x 4 x 4: for planar data the transverse sweeps are exact identities,
@@ -341,6 +387,39 @@ def test_table_eos_vs_oracle(B, torch, precision):
     np.testing.assert_allclose(p_gpu, P["p"].reshape(p_gpu.shape),
                                rtol=1e-11 if precision == 0 else 1e-5,
                                atol=1e-14)
+
+
+@pytest.mark.parametrize("precision,uniform_n", [(0, False), (1, False), (0, True)])
+def test_baryon_eos_vs_oracle(B, torch, precision, uniform_n):
+    # p = (e - m n)/3 clamped at 0: the recovery iterates with
+    # n = R sqrt(1 - v^2).  n = 0.15 e everywhere, or a uniform n with
+    # m n = 0.05 GeV/fm^3: then the background (e = 0.01) is pressureless
+    # (the clamp) and the hot spots are not
+    import oracle
+    cs2, mass = 1.0 / 3.0, 0.938
+    o = oracle.Oracle(oracle.EOS_BARYON, cs2=cs2, mass=mass)
+    prim = inputs.hotspots((31, 27, 29), 0.1, 10, seed=8, amp=(0.5, 6.0), e_bg=0.01,
+                           sigma=0.3, vz_profile=inputs.longitudinal_flow)
+    if uniform_n:
+        prim = inputs.Primitive(prim.e, prim.vx, prim.vy, prim.vz,
+                                np.full_like(prim.e, 0.05 / mass))
+    nz, ny, nx = prim.e.shape
+    s = B.Shasta([(nx, ny, nz)], 0.1, precision=precision, eos=(B.EOS_BARYON, (cs2, mass)))
+    s.write_primitive(0, *[torch.from_numpy(a) for a in prim.as_tuple()])
+    s.step(0.04, 10)
+    got = read_np(s)
+    U = to_cons(o, prim)
+    _, _, cnt = o.run(U, 0.4, 10)
+    assert cnt[2] == 0   # every oracle recovery converged
+    errs = rel_errors(got, U)
+    print("baryon", precision, uniform_n, "rel errors", errs)
+    assert max(errs) <= (TOL64 if precision == 0 else 2e-4)
+    P = o.cons_to_prim(*U)
+    if uniform_n:
+        assert (P["p"] == 0.0).any() and (P["p"] > 0.0).any()   # both sides of the clamp
+    n_gpu = s.read_field(0, "n").cpu().numpy()
+    np.testing.assert_allclose(n_gpu, P["n"].reshape(n_gpu.shape),
+                               rtol=1e-11 if precision == 0 else 1e-5, atol=1e-14)
 
 
 def test_batched_equals_single_events(B, torch):
