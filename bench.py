@@ -55,9 +55,15 @@ def measured_traffic(kernel, workload, decomposition):
         d = json.load(fh)
     if d.get("source_hash") != kernel_source_hash():
         return None
+    # the bytes depend on the windows (x: fixed by the grid, not by how many
+    # a wave takes) and on the segment length and lanes (y, z), not on the
+    # launch mode
     axis = "xyz".index(kernel[-1])
-    if d.get("decomposition", "").split("/")[axis:axis + 1] != decomposition.split("/")[axis:axis + 1]:
-        return None
+    if axis > 0:
+        mine = decomposition.split("/")[axis].split(",")[:2]
+        theirs = d.get("decomposition", "0,0,0/0,0,0/0,0,0").split("/")[axis].split(",")[:2]
+        if mine != theirs:
+            return None
     return d.get("bytes_per_launch")
 
 
