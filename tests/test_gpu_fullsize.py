@@ -228,3 +228,55 @@ def test_bag400_sampled_cells_and_mixed_bound(B, torch, orc_bag):
         err = np.abs(got32[q] - got64[q]).max() / np.abs(got64[q]).max()
         print("bag400 mixed field", q, "max rel", err)
         assert err <= 2e-4
+
+
+@pytest.mark.parametrize("precision,dims", [(0, (1023, 1024, 256)), (1, (1023, 1024, 512))])
+def test_largest_event_sampled_cells(B, torch, orc, precision, dims):
+    # the largest event shasta_create accepts: a field array just below 2^31
+    # bytes (the kernels address fields with 32-bit byte offsets); cells near
+    # the last bytes of the arrays against the oracle after one step
+    nx, ny, nz = dims
+    esize = 8 if precision == 0 else 4
+    assert nx * ny * nz * esize < 2 ** 31 <= (nx + 1) * ny * nz * esize
+    s = B.Shasta([dims], 0.2, precision=precision)
+    X, Y, Z = (torch.arange(n, dtype=torch.float64, device="cuda") for n in (nx, ny, nz))
+    e = 1.0 + 0.5 * torch.sin(0.05 * X)[None, None, :] * torch.cos(0.07 * Y)[None, :, None] \
+        * torch.sin(0.03 * Z + 0.4)[:, None, None]
+    zero = torch.zeros_like(e)
+    vz = 0.3 * torch.tanh(0.01 * (Z - nz / 2))[:, None, None].expand_as(e).contiguous()
+    s.write_primitive(0, e, zero, zero, vz, 0.15 * e)
+    del zero
+    s.set_step_index(2)
+    s.step(0.08, 1)
+    cells = [(nx - 1, ny - 1, nz - 1), (nx - 2, ny - 1, nz - 1), (nx - 1, ny - 7, nz - 3),
+             (0, ny - 1, nz - 1), (nx // 2, ny - 1, nz - 2), (nx - 1, 0, nz - 1),
+             (nx // 3, ny // 2, nz - 1), (7, 9, nz // 2), (nx - 1, ny - 1, 0)]
+    got = []
+    for q in range(5):
+        f = s.read_field(0, q)
+        got.append([f[z, y, x].item() for (x, y, z) in cells])
+        del f
+    got = np.array(got).T
+    # oracle: the +-6 box of each cell, from the same primitives (rounded to
+    # the field precision for FP32)
+    r = 6
+    ref = []
+    for (x, y, z) in cells:
+        zs = slice(max(0, z - r), min(nz, z + r + 1))
+        ys = slice(max(0, y - r), min(ny, y + r + 1))
+        xs = slice(max(0, x - r), min(nx, x + r + 1))
+        pe = e[zs, ys, xs].cpu().numpy()
+        pvz = vz[zs, ys, xs].cpu().numpy()
+        z0 = np.zeros_like(pe)
+        prim = inputs.Primitive(np.ascontiguousarray(pe), z0, z0.copy(),
+                                np.ascontiguousarray(pvz), 0.15 * pe)
+        U = to_cons(orc, prim)
+        if precision == 1:
+            U = [a.astype(np.float32).astype(np.float64) for a in U]
+        orc.run(U, 0.4, 1, k0=2)
+        ref.append([a[z - zs.start, y - ys.start, x - xs.start] for a in U])
+    ref = np.array(ref)
+    scale = [1.5, 1.0, 1.0, 1.0, 0.3]   # |E| and |R| <= 1.5 (R ~ 0.15 E gamma), |M| < 1
+    err = max(np.abs(got[:, q] - ref[:, q]).max() / scale[q] for q in range(5))
+    print("largest event, precision", precision, "max rel error", err)
+    assert err <= (TOL64 if precision == 0 else 2e-5)
