@@ -38,7 +38,8 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("shasta_kernels.hip", "shasta_math.hpp", "shasta_internal.hpp"):
+    for f in ("shasta_sweeps.hpp", "shasta_kernels.hip", "shasta_math.hpp",
+              "shasta_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1206_0919_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
