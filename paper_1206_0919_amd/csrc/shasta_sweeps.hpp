@@ -692,7 +692,9 @@ void sweep_x(SweepArgs A) {
       for (int q = 0; q < kNF; ++q) {
         b_l[q] = from_left(u[q][kXCells - 1]);
         b_r0[q] = from_right(u[q][0]);
-        b_r1[q] = from_right(u[q][1]);
+        // position of the right neighbour lane's second slot, or, with one
+        // position per lane, of the lane two to the right
+        b_r1[q] = from_right(kXCells > 1 ? u[q][1 % kXCells] : b_r0[q]);
       }
       // ---- predictor (lambda/2)
       Coef<T> k[kXCells];
