@@ -145,9 +145,30 @@ def cpu_baseline(wl, prims, budget_s=20.0):
     t0 = time.perf_counter()
     o.run(U, wl["lam"], n, k0=1)
     t = time.perf_counter() - t0
+    # the same oracle on one thread, continuing from the same state (bounded
+    # to about a third of the budget)
+    t0 = time.perf_counter()
+    o.run(U, wl["lam"], 1, k0=n + 1, nthreads=1)
+    t1s = time.perf_counter() - t0
+    n1 = max(0, min(10, int(budget_s / 3 / max(t1s, 1e-6)) - 1))
+    if n1:
+        t0 = time.perf_counter()
+        o.run(U, wl["lam"], n1, k0=n + 2, nthreads=1)
+        t1s = (time.perf_counter() - t0) / n1
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")),
+                       cpu)
+    except OSError:
+        pass
     return dict(value=cells * n / t, unit="cell-updates/s", cores=cores, kind="oracle",
                 sample=f"{wl['name']} event 0 ({dims[0]}x{dims[1]}x{dims[2]}), steps 2..{n + 1} "
-                       f"of the FP64 oracle, OpenMP over pencils, {cores} threads, {t:.1f}s")
+                       f"of the FP64 oracle, OpenMP over pencils, {cores} threads, {t:.1f}s",
+                single_thread=dict(value=cells / t1s, unit="cell-updates/s",
+                                   sample=f"{max(n1, 1)} further step(s) on 1 thread, "
+                                          f"{t1s:.1f}s per step"),
+                host=dict(cpu=cpu, nproc=os.cpu_count()))
 
 
 def parse_tiles(text):
