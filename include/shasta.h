@@ -168,11 +168,17 @@ const char* shasta_status_str(int status);
 
 /*
  * Work decomposition of the sweeps (results are bitwise independent of it).
- * axis 0 (x sweep): p0 = 4-cell windows per wave (>= 1).  axis 1, 2 (y, z
- * sweeps): p0 = segment length along the sweep axis (>= 1; the pencil is cut
- * into ceil(N/p0) segments, each recomputing a 6-cell margin), p1 = lanes
- * along x per wave (16, 32 or 64).  Rebuilds the work tables; if a workspace
- * is bound it must still be large enough (shasta_workspace_bytes tells).
+ * axis 0 (x sweep): p0 = most windows per wave (a window holds 128 positions:
+ * row pieces with a 6-cell halo each; items shrink toward the end of the
+ * launch), p1 ignored.  axis 1, 2 (y, z sweeps): p0 = segment length along
+ * the sweep axis (>= 16; the pencil is cut into ceil(N/p0) segments, each
+ * recomputing a 6-cell margin), p1 = lanes along x per wave (16, 32 or 64;
+ * the other lanes take the next rows of the transverse plane), or 1: the wave
+ * takes 64 consecutive columns of the transverse plane in x-fastest order,
+ * wrapping from the end of one row to the start of the next (no idle lane
+ * but in the plane's last wave).  0 for either = automatic (p1: 1).  Rebuilds
+ * the work tables; if a workspace is bound it must still be large enough
+ * (shasta_workspace_bytes tells).  EINVAL for other values.
  */
 int shasta_set_tiles(shasta_t* h, int axis, int p0, int p1);
 

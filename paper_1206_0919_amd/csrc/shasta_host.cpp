@@ -135,21 +135,9 @@ int64_t ncell_of(const shasta_t* h, int ev) {
   return (int64_t)h->dims[3 * ev] * h->dims[3 * ev + 1] * h->dims[3 * ev + 2];
 }
 
-// lanes along x for a y/z sweep of an event: least padding, ties to more lanes
-int auto_lanes(int nx, int nb) {
-  int best = 64;
-  double best_waste = 1e300;
-  for (int lx : {64, 32, 16}) {
-    const int lb = 64 / lx;
-    const double cells = double((nx + lx - 1) / lx) * lx * double((nb + lb - 1) / lb) * lb;
-    const double waste = cells / (double(nx) * nb);
-    if (waste < best_waste - 1e-12) {
-      best_waste = waste;
-      best = lx;
-    }
-  }
-  return best;
-}
+// Lane layout of a y/z sweep when none is set: flattened columns, which leave
+// no lane idle but in the last wave of the plane.
+int auto_lanes(int, int) { return kFlatLanes; }
 
 int lanes_for(const shasta_t* h, int axis, int ev) {
   const int nx = h->dims[3 * ev];
@@ -160,6 +148,7 @@ int lanes_for(const shasta_t* h, int axis, int ev) {
 int64_t columns(const shasta_t* h, int axis, int ev, int lx) {
   const int nx = h->dims[3 * ev];
   const int nb = (axis == 1) ? h->dims[3 * ev + 2] : h->dims[3 * ev + 1];
+  if (lx == kFlatLanes) return ((int64_t)nx * nb + 63) / 64;
   const int lb = 64 / lx;
   return (int64_t)((nx + lx - 1) / lx) * ((nb + lb - 1) / lb);
 }
@@ -232,7 +221,7 @@ void build_tables(shasta_t* h) {
         const int nx = h->dims[3 * e];
         const int nb = (ax == 1) ? h->dims[3 * e + 2] : h->dims[3 * e + 1];
         const int lx = lanes_for(h, ax, e);
-        const int lb = 64 / lx;
+        const int lb = (lx == kFlatLanes) ? 0 : 64 / lx;
         int L = h->seg[ax];
         if (L <= 0) {
           const int64_t nseg = std::max<int64_t>(
@@ -240,6 +229,21 @@ void build_tables(shasta_t* h) {
           L = (int)std::max<int64_t>(16, (N + nseg - 1) / nseg);
         }
         L = std::min(L, N);
+        if (lx == kFlatLanes) {
+          const int ncol = nx * nb;   // below 2^31: the event is
+          for (int g0 = 0; g0 < ncol; g0 += 64)
+            for (int s0 = 0; s0 < N; s0 += L) {
+              Item it{};
+              it.ev = e;
+              it.a = g0;
+              it.b = 0;
+              it.s0 = s0;
+              it.s1 = std::min(N, s0 + L);
+              it.lx = kFlatLanes;
+              it.rec = (int32_t)h->items[ax].size();
+              h->items[ax].push_back(it);
+            }
+        } else
         for (int b0 = 0; b0 < nb; b0 += lb)
           for (int x0 = 0; x0 < nx; x0 += lx)
             for (int s0 = 0; s0 < N; s0 += L) {
@@ -303,7 +307,7 @@ void table_capacity(const shasta_t* h, int64_t cap[3], int64_t& rec_cap) {
       } else {
         const int N = h->dims[3 * e + ax];
         int64_t worst = 0;
-        for (int lx : {16, 32, 64}) worst = std::max(worst, columns(h, ax, e, lx));
+        for (int lx : {kFlatLanes, 16, 32, 64}) worst = std::max(worst, columns(h, ax, e, lx));
         m = worst * ((N + 15) / 16);
       }
       n += m;
@@ -843,8 +847,10 @@ int shasta_set_tiles(shasta_t* h, int axis, int p0, int p1) {
   if (axis == 0) {
     h->xwin = p0;
   } else {
-    if (p1 != 0 && p1 != 16 && p1 != 32 && p1 != 64)
-      return fail(h, SHASTA_EINVAL, "lanes along x must be 16, 32 or 64 (0 = automatic)");
+    if (p1 != 0 && p1 != kFlatLanes && p1 != 16 && p1 != 32 && p1 != 64)
+      return fail(h, SHASTA_EINVAL,
+                  "lanes along x must be 16, 32 or 64, or 1 for flattened columns "
+                  "(0 = automatic)");
     if (p0 != 0 && p0 < 16) return fail(h, SHASTA_EINVAL, "segment length must be >= 16");
     h->seg[axis] = p0;
     h->lanes[axis] = p1;
@@ -945,7 +951,7 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
         for (int L : {16, 24, 32, 48, 64, 96, 128}) len.push_back(L);
         std::sort(len.begin(), len.end());
         len.erase(std::unique(len.begin(), len.end()), len.end());
-        for (int lx : {16, 32, 64})
+        for (int lx : {kFlatLanes, 16, 32, 64})
           for (int L : len)
             if (L >= 16 || L >= max_n) cands.push_back({std::min(L, max_n), lx, pers != 0, 0.0f});
       }

@@ -59,6 +59,8 @@ struct EventDesc {
 // R_SIZE doubles (the 13 record entries, then the non-finite probe).
 constexpr int kFinChunk = 256;
 
+constexpr int kFlatLanes = 1;      // y/z: lane layout of flattened columns
+
 // Work of one wave.
 struct Item {
   int32_t ev;   // event index, -1 = padding (wave does nothing)
@@ -68,7 +70,9 @@ struct Item {
                 //          transverse axis
   int32_t s0;   // y/z: written segment [s0, s1) along the sweep axis
   int32_t s1;
-  int32_t lx;   // y/z: lanes along x (16, 32, 64)
+  int32_t lx;   // y/z: lanes along x (16, 32, 64), or kFlatLanes: the wave
+                //      takes 64 consecutive columns of the transverse plane
+                //      (x fastest) from column a on
   int32_t rec;  // reduction record of the item (records are contiguous per
                 // event, whatever order the items are launched in)
   int32_t pad;

@@ -341,12 +341,23 @@ __device__ __forceinline__ void march_setup(M& m, const SweepArgs& A, const Item
   const int nb = (axis == 1) ? ev.n[2] : ev.n[1];
   const int s_ax = (axis == 1) ? nx : nx * ny;
   const int s_b = (axis == 1) ? nx * ny : nx;
-  const int lx_bits = __builtin_ctz(it.lx);
-  int x = it.a + (lane & (it.lx - 1));
-  int bb = it.b + (lane >> lx_bits);
-  m.active = (x < nx) && (bb < nb);
-  x = min(x, nx - 1);
-  bb = min(bb, nb - 1);
+  int x, bb;
+  if (it.lx == kFlatLanes) {
+    // 64 consecutive columns of the transverse plane, x fastest, from column
+    // it.a on (a wave may cover the end of one row and the start of the next)
+    const int g = it.a + lane;
+    m.active = g < nx * nb;
+    const int gc = min(g, nx * nb - 1);
+    bb = gc / nx;
+    x = gc - bb * nx;
+  } else {
+    const int lx_bits = __builtin_ctz(it.lx);
+    x = it.a + (lane & (it.lx - 1));
+    bb = it.b + (lane >> lx_bits);
+    m.active = (x < nx) && (bb < nb);
+    x = min(x, nx - 1);
+    bb = min(bb, nb - 1);
+  }
   m.lane = lane;
   using TT = decltype(m.lamsrc);
   m.off_col = (x + bb * s_b) * (int)sizeof(TT);

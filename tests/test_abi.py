@@ -107,6 +107,8 @@ def test_state_and_eos_validation(b):
     assert b.shasta_set_tiles(h, 2, 32, 48) == b.EINVAL  # lanes not 16/32/64
     assert b.shasta_set_tiles(h, 3, 32, 16) == b.EINVAL
     assert b.shasta_set_tiles(h, 1, 32, 16) == b.OK
+    assert b.shasta_set_tiles(h, 2, 32, 1) == b.OK      # flattened columns
+    assert b.shasta_set_tiles(h, 2, 32, 2) == b.EINVAL
     for bad_diff in (-0.1, 1.5, float("nan"), float("inf")):
         assert b.shasta_set_antidiffusion(h, bad_diff) == b.EINVAL
     for diff in (0.0, 0.5, 1.0):

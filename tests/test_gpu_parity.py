@@ -284,7 +284,12 @@ def test_decomposition_does_not_change_results(B, torch):
     for tiles, pers in (([(0, 1, 0), (1, 16, 16), (2, 16, 64)], (0, 0, 0)),
                         ([(0, 3, 0), (1, 24, 32), (2, 40, 16)], (1, 1, 1)),
                         ([(0, 0, 0), (1, 0, 0), (2, 0, 0)], (0, 1, 0)),
-                        ([(0, 16, 0), (1, 66, 64), (2, 50, 32)], (1, 0, 1))):
+                        ([(0, 16, 0), (1, 66, 64), (2, 50, 32)], (1, 0, 1)),
+                        # flattened columns: waves that span two rows of the
+                        # transverse plane, a ragged last wave (3500 and 4620
+                        # columns), both launch modes
+                        ([(0, 2, 0), (1, 20, 1), (2, 17, 1)], (0, 1, 0)),
+                        ([(0, 5, 0), (1, 66, 1), (2, 50, 1)], (1, 0, 1))):
         s = gpu_state(B, torch, prim)
         for t in tiles:
             s.set_tiles(*t)
