@@ -511,7 +511,7 @@ void sweep_march(SweepArgs A) {
 
 // ------------------------------------------------------------ x sweep
 // A window holds up to 64 kXCells positions, kXCells consecutive ones per lane
-// (two: 162 registers in FP64, three waves per SIMD).  It covers
+// (two: 116 registers in FP64, four waves per SIMD).  It covers
 // the cells [c0, c1) of the x-fastest array as row pieces, each preceded and
 // followed by 6 halo positions whose loads are clamped to the row (outflow
 // copy), exactly as the march treats the ends of a pencil.  The stencil then
@@ -624,15 +624,20 @@ void sweep_x(SweepArgs A) {
   constexpr int QP = 1, QT1 = 2, QT2 = 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ T halo[kWavesPerBlock][3][kXWindow];
+  // per-lane sums of the written cells (0..4) and boundary ledger (5..9),
+  // kept in LDS rather than registers through the item; each lane adds to
+  // its own entries in program order
+  __shared__ double xacc[kWavesPerBlock][10][64];
+  double (*const acc10)[64] = xacc[wave];
   // wave-uniform: lets the compiler keep the work item in scalar registers
   for (int kq = __builtin_amdgcn_readfirstlane(
            (int)blockIdx.x * kWavesPerBlock + wave);
        kq < A.n_items;) {
   const int item = __builtin_amdgcn_readfirstlane(item_at(A, kq));
   const Item it = A.items[item];
-  double acc[13];
 #pragma unroll
-  for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+  for (int j = 0; j < 10; ++j) acc10[j][lane] = 0.0;
+  double maxeps = 0.0;
   int n_clamp = 0, n_floor = 0;
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
@@ -719,16 +724,21 @@ void sweep_x(SweepArgs A) {
         n_clamp += out_ok[j] & (r.clamped != 0);
         n_floor += out_ok[j] & (r.floored != 0);
       }
-      // ---- U^n neighbours p-1, p+1, p+2 (kept for both half steps)
-      T b_l[kNF], b_r0[kNF], b_r1[kNF];
-#pragma unroll
-      for (int q = 0; q < kNF; ++q) {
-        b_l[q] = from_left(u[q][kXCells - 1]);
-        b_r0[q] = from_right(u[q][0]);
+      // ---- U^n neighbours p-1, p+1, p+2 of field q from the adjacent lanes
+      //      (taken again for the corrector rather than kept in registers)
+      auto neighbours = [&](int q, T (&ul)[kXCells], T (&ur)[kXCells], T (&ur2)[kXCells]) {
+        const T b_l = from_left(u[q][kXCells - 1]);
+        const T b_r0 = from_right(u[q][0]);
         // position of the right neighbour lane's second slot, or, with one
         // position per lane, of the lane two to the right
-        b_r1[q] = from_right(kXCells > 1 ? u[q][1 % kXCells] : b_r0[q]);
-      }
+        const T b_r1 = from_right(kXCells > 1 ? u[q][1 % kXCells] : b_r0);
+#pragma unroll
+        for (int j = 0; j < kXCells; ++j) {
+          ul[j] = (j > 0) ? u[q][j - 1] : b_l;
+          ur[j] = (j < kXCells - 1) ? u[q][j + 1] : b_r0;
+          ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0 : b_r1);
+        }
+      };
       // ---- predictor (lambda/2)
       Coef<T> k[kXCells];
       T sE[kXCells], sM[kXCells];
@@ -737,13 +747,9 @@ void sweep_x(SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
         T ul[kXCells], ur[kXCells], ur2[kXCells], s[kXCells];
+        neighbours(q, ul, ur, ur2);
 #pragma unroll
-        for (int j = 0; j < kXCells; ++j) {
-          ul[j] = (j > 0) ? u[q][j - 1] : b_l[q];
-          ur[j] = (j < kXCells - 1) ? u[q][j + 1] : b_r0[q];
-          ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0[q] : b_r1[q]);
-          s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
-        }
+        for (int j = 0; j < kXCells; ++j) s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
         x_fct<antiflux_of<EOS>>(u[q], ul, ur, ur2, k, s, diff8, uh[q]);
       }
       // ---- recovery at U^{n+1/2}; halo positions take their edge cell's
@@ -760,7 +766,7 @@ void sweep_x(SweepArgs A) {
         fMc[j] = T(r.p);
         n_clamp += out_ok[j] & (r.clamped != 0);
         n_floor += out_ok[j] & (r.floored != 0);
-        acc[R_MAXEPS] = out_ok[j] ? fmax(acc[R_MAXEPS], fabs(double(ec[j]))) : acc[R_MAXEPS];
+        maxeps = out_ok[j] ? fmax(maxeps, fabs(double(ec[j]))) : maxeps;
         // table entry of position p at (p % kXCells) * 64 + p / kXCells:
         // a wave's writes and own-position reads touch distinct banks
         hE[j * 64 + lane] = ec[j];
@@ -789,19 +795,17 @@ void sweep_x(SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
         T ul[kXCells], ur[kXCells], ur2[kXCells], s[kXCells], out[kXCells];
+        neighbours(q, ul, ur, ur2);
 #pragma unroll
-        for (int j = 0; j < kXCells; ++j) {
-          ul[j] = (j > 0) ? u[q][j - 1] : b_l[q];
-          ur[j] = (j < kXCells - 1) ? u[q][j + 1] : b_r0[q];
-          ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0[q] : b_r1[q]);
-          s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
-        }
+        for (int j = 0; j < kXCells; ++j) s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
         x_fct<antiflux_of<EOS>>(u[q], ul, ur, ur2, k, s, diff8, out);
+        double sum = acc10[R_SUM + q][lane];
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) {
           buf_store<T>(dst[q], out_ok[j] ? cell[j] * (int)sizeof(T) : kDropOffset, out[j]);
-          acc[R_SUM + q] += out_ok[j] ? double(out[j]) : 0.0;
+          sum += out_ok[j] ? double(out[j]) : 0.0;
         }
+        acc10[R_SUM + q][lane] = sum;
       }
       // boundary ledger: flux through the outflow faces (corrector)
 #pragma unroll
@@ -812,13 +816,19 @@ void sweep_x(SweepArgs A) {
           for (int q = 0; q < kNF; ++q) {
             const double f = (q == 0) ? double(fEc[j]) : ((q == QP) ? double(fMc[j]) : 0.0);
             const double F = face_flux(double(ec[j]), double(u[q][j]), lam, f);
-            acc[R_LEDGER + q] = last ? acc[R_LEDGER + q] + F : acc[R_LEDGER + q];
-            acc[R_LEDGER + q] = first ? acc[R_LEDGER + q] - F : acc[R_LEDGER + q];
+            double l = acc10[R_LEDGER + q][lane];
+            l = last ? l + F : l;
+            l = first ? l - F : l;
+            acc10[R_LEDGER + q][lane] = l;
           }
         }
       }
     }
   }
+  double acc[13];
+#pragma unroll
+  for (int j = 0; j < 10; ++j) acc[j] = acc10[j][lane];
+  acc[R_MAXEPS] = maxeps;
   acc[R_CLAMP] = double(n_clamp);
   acc[R_FLOOR] = double(n_floor);
   wave_record(acc, A.rec, it.rec);
