@@ -170,18 +170,38 @@ struct MarchCommon {
 template <typename T, int AXIS, int EOS>
 struct MarchP : MarchCommon<T, AXIS, EOS> {
   using C = MarchCommon<T, AXIS, EOS>;
-  T u[kNF][8], d[kNF][8], hp[kNF][8], gp[kNF][8], ap[kNF][8];
+  // FP32: U^n rows i-2 .. i-4 are read back from the LDS ring (written by
+  // this wave in earlier trips) and their differences taken again, instead
+  // of holding a ring of Delta in registers: 135 -> 115 registers, four
+  // pairs per SIMD.  FP64 keeps the register ring (the re-reads slowed the
+  // FP64 march, which stays at three pairs per SIMD either way).
+  static constexpr bool kReread = sizeof(T) == 4;
+  T u[kNF][8], d[kNF][kReread ? 1 : 8], hp[kNF][8], gp[kNF][8], ap[kNF][8];
   T ep[8], fE[8], fM[8], rd[8];
   __amdgpu_buffer_rsrc_t src[kNF];
   int off_col, step_bytes;
 
-  __device__ __forceinline__ void init() {
+  // Registers start at zero, and so do the U^n ring rows P reads back
+  // before it has written them (rows before the segment's first trip), so
+  // both forms see the same values there.
+  template <class Ring>
+  __device__ __forceinline__ void init(Ring& L) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       ep[j] = fE[j] = fM[j] = T(0);
       rd[j] = T(1);
 #pragma unroll
-      for (int q = 0; q < kNF; ++q) u[q][j] = d[q][j] = hp[q][j] = gp[q][j] = ap[q][j] = T(0);
+      for (int q = 0; q < kNF; ++q) {
+        u[q][j] = hp[q][j] = gp[q][j] = ap[q][j] = T(0);
+        if constexpr (!kReread) d[q][j] = T(0);
+      }
+    }
+    if constexpr (kReread) {
+      constexpr int U = MarchCfg<T, EOS>::un_slots;
+#pragma unroll
+      for (int r = 0; r < U; ++r)
+#pragma unroll
+        for (int q = 0; q < kNF; ++q) L.un[r][q][this->lane] = T(0);
     }
   }
   template <int PH>
@@ -217,13 +237,29 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
     const Coef<T> kp = coefficients(ep[S1], rd[S1], rd[S0]);
     const T sE = source(this->lamsrc, fE[S2], fE[S0]);
     const T sM = source(this->lamsrc, fM[S2], fM[S0]);
+    constexpr int U = MarchCfg<T, EOS>::un_slots;
+    const int r2 = (uslot + U - 2) % U, r3 = (uslot + U - 3) % U, r4 = (uslot + U - 4) % U;
 #pragma unroll
     for (int q = 0; q < kNF; ++q) {
       const T s = (q == 0) ? sE : ((q == QP) ? sM : T(0));
-      d[q][S1] = u[q][S0] - u[q][S1];                                    // Delta_{i-1}
-      hp[q][S1] = transport(kp, s, d[q][S1], d[q][S2], u[q][S1]);        // hat U_{i-1}
+      T d1, d2, d3, d4;                                   // Delta_{i-1} .. Delta_{i-4}
+      if constexpr (kReread) {
+        const T u2 = L.un[r2][q][this->lane], u3 = L.un[r3][q][this->lane],
+                u4 = L.un[r4][q][this->lane];
+        d1 = u[q][S0] - u[q][S1];
+        d2 = u[q][S1] - u2;
+        d3 = u2 - u3;
+        d4 = u3 - u4;
+      } else {
+        d[q][S1] = u[q][S0] - u[q][S1];
+        d1 = d[q][S1];
+        d2 = d[q][S2];
+        d3 = d[q][S3];
+        d4 = d[q][S4];
+      }
+      hp[q][S1] = transport(kp, s, d1, d2, u[q][S1]);                    // hat U_{i-1}
       gp[q][S2] = hp[q][S1] - hp[q][S2];                                 // hat Delta_{i-2}
-      const T sec = second_difference(d[q][S2], d[q][S4], d[q][S3]);    // at i-3
+      const T sec = second_difference(d2, d4, d3);                       // at i-3
       if constexpr (antiflux_of<EOS>)
         ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], sec, this->diff8);
       else
@@ -418,7 +454,7 @@ void sweep_march(SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < kNF; ++q)
         P.src[q] = field_rsrc(base + ev.off[A.parity] + q * ev.pitch, fbytes);
-      P.init();
+      P.init(L);
       P.template load<0>(i_lo);
       if constexpr (kPrefetch >= 2) P.template load<1>(i_lo + 1);
       if constexpr (kPrefetch >= 3) P.template load<2>(i_lo + 2);
