@@ -654,8 +654,11 @@ __device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCel
   for (int j = 0; j < kXCells; ++j) out[j] = update(uh[j], a[j], (j > 0) ? a[j - 1] : al);
 }
 
+// FP32 grid launch: five waves per SIMD (96 registers, 2 % faster than four);
+// the other forms spill at that limit and keep the compiler's choice.
 template <typename T, int EOS, bool PERSIST>
 __global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !PERSIST ? 5 : 1)))
 void sweep_x(SweepArgs A) {
   constexpr int QP = 1, QT1 = 2, QT2 = 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
