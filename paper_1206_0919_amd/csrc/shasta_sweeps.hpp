@@ -7,16 +7,17 @@
 // U^{n+1/2}, lambda corrector from U^n (Sec. 3, eqs. shasta-diff..shasta-n;
 // Sec. 3.1 half-step method, halo cells; Listing 2 order).  Each sweep reads
 // the five conserved fields once and writes them once; every intermediate
-// stays in registers.
+// stays on chip (registers and LDS).
 //
-//  - y and z sweeps (sweep_march): a lane owns one column across the x axis
-//    (lanes are consecutive in x, so every load and store is coalesced) and
-//    marches along the sweep axis through a software pipeline.  Cell i of
-//    U^n enters at iteration i; U^{n+1/2} of cell i-3 and U^{n+1} of cell i-6
+//  - y and z sweeps (sweep_march): a lane owns one column of the transverse
+//    plane (lanes are consecutive in x, so every load and store is
+//    coalesced) and marches along the sweep axis through a software
+//    pipeline split over a producer and a consumer wave.  Cell i of U^n
+//    enters at iteration i; U^{n+1/2} of cell i-3 and U^{n+1} of cell i-6
 //    leave in the same iteration, so each quantity is computed once.
 //  - x sweep (sweep_x): a lane owns kXCells (2) consecutive positions of a
 //    window of 64 kXCells positions that holds row pieces with their halos;
-//    neighbours come from the adjacent lane through cross-lane shuffles.
+//    neighbours come from the adjacent lane through DPP wave shifts.
 //
 // Both organisations call the same arithmetic (shasta_math.hpp) with the
 // same operands, so an x sweep and a y or z sweep of transposed data agree
@@ -28,9 +29,6 @@
 #include "shasta_math.hpp"
 
 namespace shasta {
-
-
-
 
 // The scheme a sweep kernel is compiled for: the EOS kind in the low bits,
 // kNoAntiflux set for the kernels without the phoenical antiflux and its
@@ -129,8 +127,10 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 // Configuration of the march per precision and EOS.  FP64 on the ideal gas
 // runs three pairs per SIMD: 168 registers and 23 KB of LDS per pair, which
 // needs a barrier every trip (S = 1) and one row of prefetch.  The others
-// keep S = 2 and two rows of prefetch: FP32 fits three pairs anyway, FP64 on
-// the bag and tabled EOS need more registers than three pairs allow.
+// keep S = 2 and two rows of prefetch: FP32 fits three pairs anyway (four on
+// the ideal gas and the bag model, with the producer's LDS re-reads), FP64
+// on the bag, tabled and baryon EOS need more registers than three pairs
+// allow.
 template <typename T, int EOS>
 struct MarchCfg {
   static constexpr bool tight = sizeof(T) == 8 && eos_of<EOS> == 0;
