@@ -36,12 +36,43 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def code_tokens(src):
+    """C/C++ source without comments, whitespace runs collapsed to one space
+    (string and character literals kept as written)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the kernel sources as code: comments and layout do not count,
+    so a counter summary stays valid across edits that change neither."""
     h = hashlib.sha256()
     for f in ("shasta_sweeps.hpp", "shasta_kernels.hip", "shasta_math.hpp",
               "shasta_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1206_0919_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_1206_0919_amd", "csrc", f)) as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(code_tokens(text).encode())
     return h.hexdigest()[:16]
 
 
