@@ -78,8 +78,9 @@ def kernel_source_hash(read=None):
 
 def measured_traffic(kernel, workload, decomposition):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources with the same decomposition of the
-    kernel's axis; else None."""
+    was taken on the current kernel code with a decomposition that gives the
+    kernel's axis the same bytes; else None."""
+    from paper_1206_0919_amd.profsum import axis_key
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -87,16 +88,12 @@ def measured_traffic(kernel, workload, decomposition):
         d = json.load(fh)
     if d.get("source_hash") != kernel_source_hash():
         return None
-    # the bytes depend on the windows (x: fixed by the grid, not by how many
-    # a wave takes) and on the segment length and lanes (y, z), not on the
-    # launch mode
     axis = "xyz".index(kernel[-1])
-    if axis > 0:
-        mine = decomposition.split("/")[axis].split(",")[:2]
-        theirs = d.get("decomposition", "0,0,0/0,0,0/0,0,0").split("/")[axis].split(",")[:2]
-        if mine != theirs:
-            return None
-    return d.get("bytes_per_launch")
+    key = axis_key(decomposition, axis)
+    for e in d.get("entries", []):
+        if axis_key(e["decomposition"], axis) == key:
+            return e["bytes_per_launch"]
+    return None
 
 
 def copy_ceiling(torch, B, mib=1024, reps=10):

@@ -92,28 +92,49 @@ def per_dispatch(d, counter):
     return {k: sum(v.values()) / len(v) for k, v in acc.items()}
 
 
+def axis_key(decomposition, axis):
+    """The part of a decomposition ('p0,p1,pers/...') that sets a sweep's
+    HBM bytes: nothing for x (its windows are fixed by the grid), segment
+    length and lanes for y and z (not the launch mode)."""
+    if axis == 0:
+        return ""
+    return ",".join(decomposition.split("/")[axis].split(",")[:2])
+
+
 def traffic(fetch_dir, write_dir, workload, fetch_scale, write_scale, out_dir, decomposition):
-    """Write profiles/traffic_<kernel>_<workload>.json: HBM bytes per launch
-    = fetch_scale * FETCH_SIZE + write_scale * WRITE_SIZE (KiB), tagged with
-    the hash of the kernel sources and the decomposition they were measured
-    on."""
+    """Add to profiles/traffic_<kernel>_<workload>.json the HBM bytes per
+    launch = fetch_scale * FETCH_SIZE + write_scale * WRITE_SIZE (KiB) of one
+    decomposition, next to the entries of other decompositions measured on
+    the same kernel code (a file of other code is started afresh)."""
     import json
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from bench import kernel_source_hash
     fe = per_dispatch(fetch_dir, "FETCH_SIZE")
     wr = per_dispatch(write_dir, "WRITE_SIZE")
+    code = kernel_source_hash()
     for k in fe:
         if not k.startswith("sweep") or k not in wr:
             continue
         base = k.split("<")[0]
-        rec = {"kernel": k, "workload": workload, "fetch_KiB": fe[k], "write_KiB": wr[k],
-               "fetch_scale": fetch_scale, "write_scale": write_scale,
-               "bytes_per_launch": 1024 * (fetch_scale * fe[k] + write_scale * wr[k]),
-               "source_hash": kernel_source_hash(), "decomposition": decomposition}
+        axis = "xyz".index(base[-1])
         path = os.path.join(out_dir, f"traffic_{base}_{workload}.json")
+        rec = {"kernel": k, "workload": workload, "source_hash": code,
+               "fetch_scale": fetch_scale, "write_scale": write_scale, "entries": []}
+        if os.path.exists(path):
+            with open(path) as fh:
+                old = json.load(fh)
+            if old.get("source_hash") == code and "entries" in old:
+                rec["entries"] = old["entries"]
+        key = axis_key(decomposition, axis)
+        rec["entries"] = [e for e in rec["entries"]
+                          if axis_key(e["decomposition"], axis) != key]
+        entry = {"decomposition": decomposition, "fetch_KiB": fe[k], "write_KiB": wr[k],
+                 "bytes_per_launch": 1024 * (fetch_scale * fe[k] + write_scale * wr[k])}
+        rec["entries"].append(entry)
+        rec["entries"].sort(key=lambda e: e["decomposition"])
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=1)
-        print(path, rec["bytes_per_launch"])
+        print(path, decomposition, entry["bytes_per_launch"])
 
 
 if __name__ == "__main__":

@@ -39,18 +39,22 @@ def test_source_hash_ignores_comments_but_not_code():
 def test_measured_traffic_matches_hash_and_decomposition(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    rec = {"bytes_per_launch": 1.5e9, "source_hash": bench.kernel_source_hash(),
-           "decomposition": "8,0,0/100,1,1/67,64,0"}
+    code = bench.kernel_source_hash()
+    entries = [{"decomposition": "8,0,0/100,1,1/67,64,0", "bytes_per_launch": 1.5e9},
+               {"decomposition": "8,0,0/50,1,0/200,1,0", "bytes_per_launch": 1.7e9}]
     for k in "xyz":
-        (prof / f"traffic_sweep_{k}_w.json").write_text(json.dumps(rec))
+        (prof / f"traffic_sweep_{k}_w.json").write_text(
+            json.dumps({"source_hash": code, "entries": entries}))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: rec["source_hash"])
-    # x: any decomposition (the windows are fixed by the grid)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: code)
+    # x: any decomposition (the windows are fixed by the grid): first entry
     assert bench.measured_traffic("sweep_x", "w", "32,0,1/1,1,1/1,1,1") == 1.5e9
     # y, z: segment length and lanes must match; the launch mode need not
     assert bench.measured_traffic("sweep_y", "w", "2,0,0/100,1,0/1,1,1") == 1.5e9
-    assert bench.measured_traffic("sweep_y", "w", "2,0,0/50,1,1/1,1,1") is None
+    assert bench.measured_traffic("sweep_y", "w", "2,0,0/50,1,1/1,1,1") == 1.7e9
+    assert bench.measured_traffic("sweep_y", "w", "2,0,0/67,1,1/1,1,1") is None
     assert bench.measured_traffic("sweep_z", "w", "2,0,0/1,1,1/67,64,1") == 1.5e9
+    assert bench.measured_traffic("sweep_z", "w", "2,0,0/1,1,1/200,1,1") == 1.7e9
     assert bench.measured_traffic("sweep_z", "w", "2,0,0/1,1,1/67,32,0") is None
     assert bench.measured_traffic("sweep_x", "other", "8,0,0/1,1,1/1,1,1") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
