@@ -274,12 +274,16 @@ def test_conservation_ledger(B, torch):
     assert r["t"] == pytest.approx(40 * DT, rel=1e-14)
 
 
-def test_decomposition_does_not_change_results(B, torch):
+# FP64 ideal gas (register rings), FP32 ideal gas and bag model (the march
+# producer reads U^n rows back from its LDS ring)
+@pytest.mark.parametrize("precision,bag", [(0, False), (1, False), (1, True)])
+def test_decomposition_does_not_change_results(B, torch, precision, bag):
     rng = np.random.default_rng(9)
     dims = (70, 66, 50)
     pr = inputs.hotspots(dims, DX, 8, seed=9)
     v = rng.uniform(-0.3, 0.3, (3,) + pr.e.shape)
     prim = inputs.Primitive(pr.e, v[0], v[1], v[2], pr.n)
+    eos = (B.EOS_BAG, inputs.bag_parameters()) if bag else None
     outs = []
     for tiles, pers in (([(0, 1, 0), (1, 16, 16), (2, 16, 64)], (0, 0, 0)),
                         ([(0, 3, 0), (1, 24, 32), (2, 40, 16)], (1, 1, 1)),
@@ -290,7 +294,7 @@ def test_decomposition_does_not_change_results(B, torch):
                         # columns), both launch modes
                         ([(0, 2, 0), (1, 20, 1), (2, 17, 1)], (0, 1, 0)),
                         ([(0, 5, 0), (1, 66, 1), (2, 50, 1)], (1, 0, 1))):
-        s = gpu_state(B, torch, prim)
+        s = gpu_state(B, torch, prim, precision=precision, eos=eos)
         for t in tiles:
             s.set_tiles(*t)
         for ax, p in enumerate(pers):
