@@ -24,9 +24,10 @@
  *     order of the permutation table of the enqueueing listing (Appendix A,
  *     Listing 2), cycling with period 6 steps;
  *   - the predictor (half step, lambda/2) applies transport, antidiffusion and
- *     limiter like the full step (Sec. 3.1, "half-step method", Listing 2);
+ *     limiter like the full step (Sec. 3.1, the half-step method; Listing 2);
  *   - the corrector restarts from U^n with the half-step velocity and source
- *     (Sec. 3, eq. shasta-diff: "v staggered in time"; source at n+1/2);
+ *     (Sec. 3, eq. shasta-diff, with v taken half a step later; source at
+ *     n+1/2);
  *   - boundaries: three halo cells per side (Sec. 3.1, halo cells), filled by
  *     copying the edge cell (outflow) before each half step;
  *   - the eigenframe recovery is a fixed-point iteration (Sec. 3, last
@@ -34,7 +35,15 @@
  *     most 2^-50, at most 200 iterations; an admissibility guard
  *     E >= 1e-300, |M| <= (1 - 1e-10) E is applied inside the recovery only
  *     and counted, the conserved fields are never modified by it;
- *   - the velocity points along M (eq. cf-momentum).
+ *   - the velocity points along M (eq. cf-momentum);
+ *   - the constant diff scales the phoenical antiflux (1 by default); the
+ *     runs without antiflux are diff = 0 (Sec. 3.1, Sec. 4);
+ *   - a tabled EOS is linear between its nodes, the last segment continuing
+ *     past the last node (Sec. 3, where the recovery is written for an
+ *     arbitrary p(e));
+ *   - the baryon-dependent EOS is p = cs2 max(0, e - m n) with the rest-frame
+ *     density n = R sqrt(1 - v^2) updated inside the fixed point (Sec. 3, the
+ *     recovery of (e, n) from (E, M, R)).
  */
 #include <math.h>
 #include <stdint.h>
@@ -53,7 +62,7 @@
 enum { ORC_NF = 5 };
 
 /* Equation of state.  kind 0: ideal ultra-relativistic gas p = e/3
- * (Sec. 2, closure "ideal gas").  kind 1: bag model with a first order phase
+ * (Sec. 2, the ideal-gas closure).  kind 1: bag model with a first order phase
  * transition: p = e/3 below e_H, p = e_H/3 in the mixed phase
  * e_H < e < e_Q = e_H + 4B, p = (e - 4B)/3 above (the paper leaves the EOS
  * open and mentions tabled ones; this is the standard bag closure).
