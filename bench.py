@@ -232,8 +232,11 @@ def run_workload(torch, B, name, steps, warmup, autotune=True, profile_steps=12,
     torch.cuda.synchronize()
     log(f"{name}: warmup {warmup} steps done; timing {steps} steps")
     ms = time_steps(torch, s, dt, steps)
+    # five more timed repetitions (a fifth of the steps each) for the spread
+    rsteps = max(20, steps // 5)
+    reps = [time_steps(torch, s, dt, rsteps) / rsteps for _ in range(5)]
     prof = kernel_profile(torch, s, dt, profile_steps)
-    return s, prims, wl, cells, ms, prof, precision
+    return s, prims, wl, cells, ms, prof, precision, (rsteps, reps)
 
 
 def main():
@@ -261,7 +264,7 @@ def main():
     from paper_1206_0919_amd import binding as B
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    s, prims, wl, cells, ms, prof, precision = run_workload(
+    s, prims, wl, cells, ms, prof, precision, (rsteps, reps) = run_workload(
         torch, B, args.workload, args.steps, args.warmup, not args.no_autotune,
         tiles=parse_tiles(args.tiles) if args.tiles else None)
     value = cells * args.steps / (ms / 1000.0)
@@ -283,6 +286,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "repeats": {"steps_each": rsteps, "ms_per_step": reps,
+                    "median_ms_per_step": sorted(reps)[len(reps) // 2]},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -310,7 +315,7 @@ def main():
         for name in ("shock256_mixed", "batch96"):
             v = run_workload(torch, B, name, max(20, args.steps // 5), args.warmup,
                              not args.no_autotune)
-            vs, _, vwl, vcells, vms, vprof, vprec = v
+            vs, _, vwl, vcells, vms, vprof, vprec, _ = v
             vsteps = max(20, args.steps // 5)
             vsw = {k: x for k, x in vprof.items() if k.startswith("sweep") and x["launches"]}
             vdom = max(vsw, key=lambda k: vsw[k]["ms_total"])
@@ -325,7 +330,7 @@ def main():
         # the paper's runs without anti-flux: same workload, transport only;
         # the difference is the cost of the antiflux and its limiter
         nsteps = max(20, args.steps // 5)
-        ns, _, _, ncells, nms, nprof, _ = run_workload(torch, B, args.workload, nsteps,
+        ns, _, _, ncells, nms, nprof, _, _ = run_workload(torch, B, args.workload, nsteps,
                                                        args.warmup, not args.no_autotune,
                                                        diff=0.0)
         rec["variants"][args.workload + "_without_antiflux"] = {
