@@ -478,6 +478,13 @@ void sweep_march(SweepArgs A) {
       acc[R_FLOOR] = P.active ? double(P.n_floor) : 0.0;
     } else {
       MarchC<T, AXIS, EOS> Cw;
+      // FP64 ideal gas (a barrier every trip): the consumer issues ahead of
+      // the other waves on its SIMD, since every trip ends at a barrier with
+      // its producer and the consumer has the longer trip (y/z sweeps
+      // 183-185 -> 174-177 us on 200^3).  With a barrier every two trips
+      // (FP32, other EOS) the same priority slowed the sweeps (bag400 FP32
+      // 976 -> 1045 us), so they keep the default.
+      if constexpr (MarchCfg<T, EOS>::tight) __builtin_amdgcn_s_setprio(2);
       march_setup(Cw, A, it, ev, AXIS, lane);
       Cw.lamsrc = T(-0.5 * A.lam);   // -lambda'/2 with lambda' = lambda
 #pragma unroll
@@ -743,7 +750,10 @@ void sweep_x(SweepArgs A) {
     for (int w = it.a; w < it.a + it.b; ++w) {
       const XMap m = map_window(w);
       T u[kNF][kXCells];
+      // loads of the window issue ahead of the other waves' arithmetic
+      __builtin_amdgcn_s_setprio(2);
       load_window(m, u);
+      __builtin_amdgcn_s_setprio(0);
       const int (&cell)[kXCells] = m.cell;
       const int (&xs)[kXCells] = m.xs;
       const bool (&used)[kXCells] = m.used;
