@@ -306,6 +306,33 @@ def test_decomposition_does_not_change_results(B, torch, precision, bag):
             assert np.array_equal(outs[0][q], o[q])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_random_decompositions_bitwise(B, torch, precision):
+    # a ragged grid (no axis a multiple of 16 or 64) under seeded random
+    # decompositions: segment lengths from 16 to the whole pencil, every lane
+    # layout, 1-32 windows per wave, either launch mode per axis
+    rng = np.random.default_rng(17 + precision)
+    dims = (45, 38, 29)
+    pr = inputs.hotspots(dims, DX, 6, seed=21)
+    v = rng.uniform(-0.35, 0.35, (3,) + pr.e.shape)
+    prim = inputs.Primitive(pr.e, v[0], v[1], v[2], pr.n)
+    ref_state = gpu_state(B, torch, prim, precision=precision)
+    ref_state.step(DT, 7)
+    ref = read_np(ref_state)
+    n = {1: dims[1], 2: dims[2]}
+    for trial in range(6):
+        s = gpu_state(B, torch, prim, precision=precision)
+        s.set_tiles(0, int(rng.integers(1, 33)), 0)
+        for ax in (1, 2):
+            s.set_tiles(ax, int(rng.integers(16, n[ax] + 1)), int(rng.choice([1, 16, 32, 64])))
+        for ax in range(3):
+            s.set_persistent(ax, int(rng.integers(0, 2)))
+        s.step(DT, 7)
+        got = read_np(s)
+        for q in range(5):
+            assert np.array_equal(ref[q], got[q]), (trial, s.decomposition(), q)
+
+
 def test_graph_replay_matches_direct_launches(B, torch):
     prim = inputs.hotspots((40, 40, 40), DX, 8, seed=3)
     sd = gpu_state(B, torch, prim)
