@@ -275,6 +275,36 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
   return r;
 }
 
+// ------------------------------------------------------------ typed helpers
+// Fused multiply-add, min, max, |x| and copysign in the precision of their
+// operands: the FCT of the FP32 fields runs in FP32 (the unsuffixed builtins
+// are the double versions and would promote float operands).
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+template <typename T>
+__device__ __forceinline__ T fmin_t(T a, T b) {
+  if constexpr (sizeof(T) == 4) return __builtin_fminf(a, b);
+  else return __builtin_fmin(a, b);
+}
+template <typename T>
+__device__ __forceinline__ T fmax_t(T a, T b) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaxf(a, b);
+  else return __builtin_fmax(a, b);
+}
+template <typename T>
+__device__ __forceinline__ T fabs_t(T a) {
+  if constexpr (sizeof(T) == 4) return __builtin_fabsf(a);
+  else return __builtin_fabs(a);
+}
+template <typename T>
+__device__ __forceinline__ T copysign_t(T a, T b) {
+  if constexpr (sizeof(T) == 4) return __builtin_copysignf(a, b);
+  else return __builtin_copysign(a, b);
+}
+
 // ------------------------------------------------------------ SHASTA pieces
 // Geometric factors (eq. shasta-diff) share one reciprocal per interface:
 // Q+_j = (1/2 - eps_j) / D_{j+1/2},  Q-_j = (1/2 + eps_j) / D_{j-1/2},
@@ -314,8 +344,7 @@ __device__ __forceinline__ T source(T lamsrc, T f_left, T f_right) {
 template <typename T>
 __device__ __forceinline__ T transport(const Coef<T>& k, T src, T d_right,
                                        T d_left, T u) {
-  return __builtin_fma(k.a, d_right,
-                       __builtin_fma(-k.b, d_left, __builtin_fma(k.c, u, src)));
+  return fma_t(k.a, d_right, fma_t(-k.b, d_left, fma_t(k.c, u, src)));
 }
 
 // Second difference of Delta used by the phoenical antidiffusion.
@@ -331,11 +360,10 @@ __device__ __forceinline__ T second_difference(T d_next, T d_prev, T d) {
 template <typename T>
 __device__ __forceinline__ T limited_antiflux(T dh_prev, T dh, T dh_next,
                                              T second, T diff8) {
-  const T aph = diff8 * __builtin_fma(T(-0.125), second, dh);
-  const T sg = __builtin_copysign(T(1), aph);
-  const T m = __builtin_fmin(__builtin_fmin(sg * dh_next, __builtin_fabs(aph)),
-                             sg * dh_prev);
-  return __builtin_copysign(__builtin_fmax(T(0), m), aph);
+  const T aph = diff8 * fma_t(T(-0.125), second, dh);
+  const T sg = copysign_t(T(1), aph);
+  const T m = fmin_t(fmin_t(sg * dh_next, fabs_t(aph)), sg * dh_prev);
+  return copysign_t(fmax_t(T(0), m), aph);
 }
 
 // Update (eq. shasta-n): U^{n+1}_j = hat U_j - (A_j - A_{j-1}).
