@@ -112,9 +112,10 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 //               stores, reductions.
 // P hands U^n and U^{n+1/2} to C through LDS rings.  The pair meets at a
 // barrier every S iterations and C runs S iterations behind P: at trip t P
-// writes U^n slot t mod (2S + 3) and U^{n+1/2} slot t mod 2S while C reads
-// U^n slot (t - S - 3) mod (2S + 3) and U^{n+1/2} slot (t - S) mod 2S, all
-// written before the previous barrier and not rewritten before the next one.
+// writes U^n slot t mod U and U^{n+1/2} slot t mod 2S while C reads U^n
+// slot (t - S - 3) mod U and U^{n+1/2} slot (t - S) mod 2S, all written
+// before the previous barrier and not rewritten before the next one (this
+// needs U >= 2S + 3 ring slots for U^n).
 // Each wave carries about half of the pipeline state.
 //
 // Every windowed quantity lives in a ring of 8 slots: the value of cell p is
@@ -137,14 +138,20 @@ struct MarchCfg {
   static constexpr int sync = tight ? 1 : 2;        // trips between barriers
   static constexpr int prefetch = tight ? 1 : 2;    // rows P loads ahead
   static constexpr int waves = (sizeof(T) == 8 && eos_of<EOS> != 0) ? 2 : 3;  // per SIMD
-  static constexpr int un_slots = 2 * sync + 3;     // U^n rows between P and C
+  // U^n rows between P and C: at least 2S + 3.  FP64 takes eight, so that
+  // with loop chunks of 8 trips every slot index is a compile-time constant
+  // (the run-time slot arithmetic made the march spill 28-38 scalar
+  // registers; y/z sweeps 182-184 -> 178-181 us on 200^3).  FP32 keeps
+  // 2S + 3: the longer ring cost it a pair per CU (shock256 6 % slower).
+  static constexpr int un_slots = sizeof(T) == 8 ? 8 : 2 * sync + 3;
   static_assert(sync == 1 || sync == 2, "the 8-phase loop body needs S in {1, 2}");
+  static_assert(un_slots >= 2 * sync + 3, "ring too short for the lag between P and C");
   static_assert(prefetch >= 1 && prefetch <= 3, "register ring of 8: lifetime 4 + prefetch");
 };
 
-template <typename T, int S>
+template <typename T, int S, int U>
 struct RingLds {
-  T un[2 * S + 3][kNF][64];  // U^n rows, slot = loop trip mod (2S + 3)
+  T un[U][kNF][64];          // U^n rows, slot = loop trip mod U
   T uh[2 * S][kNF][64];      // U^{n+1/2} rows, slot = loop trip mod 2S
   // C's per-lane FP64 accumulators of the written cells' sums and of the
   // boundary ledger: kept in LDS, not in registers, through the whole march
@@ -418,7 +425,7 @@ void sweep_march(SweepArgs A) {
   constexpr int kSync = MarchCfg<T, EOS>::sync;
   constexpr int kUnSlots = MarchCfg<T, EOS>::un_slots;
   constexpr int kPrefetch = MarchCfg<T, EOS>::prefetch;
-  __shared__ RingLds<T, kSync> L;
+  __shared__ RingLds<T, kSync, kUnSlots> L;
   __shared__ double part[16];
   __shared__ int next;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
