@@ -138,12 +138,14 @@ struct MarchCfg {
   static constexpr int sync = tight ? 1 : 2;        // trips between barriers
   static constexpr int prefetch = tight ? 1 : 2;    // rows P loads ahead
   static constexpr int waves = (sizeof(T) == 8 && eos_of<EOS> != 0) ? 2 : 3;  // per SIMD
-  // U^n rows between P and C: at least 2S + 3.  FP64 takes eight, so that
-  // with loop chunks of 8 trips every slot index is a compile-time constant
-  // (the run-time slot arithmetic made the march spill 28-38 scalar
-  // registers; y/z sweeps 182-184 -> 178-181 us on 200^3).  FP32 keeps
-  // 2S + 3: the longer ring cost it a pair per CU (shock256 6 % slower).
-  static constexpr int un_slots = sizeof(T) == 8 ? 8 : 2 * sync + 3;
+  // U^n rows between P and C: at least 2S + 3; eight, so that with loop
+  // chunks of 8 trips every slot index is a compile-time constant (the
+  // run-time slot arithmetic made the march spill 28-41 scalar registers;
+  // FP64 y/z sweeps 182-184 -> 178-181 us on 200^3).
+  static constexpr int un_slots = 8;
+  // C's boundary ledger: in LDS for FP64 (registers are the limit there), in
+  // registers for FP32, whose 8-row ring would otherwise cost it a pair per CU
+  static constexpr bool ledger_in_lds = sizeof(T) == 8;
   static_assert(sync == 1 || sync == 2, "the 8-phase loop body needs S in {1, 2}");
   static_assert(un_slots >= 2 * sync + 3, "ring too short for the lag between P and C");
   static_assert(prefetch >= 1 && prefetch <= 3, "register ring of 8: lifetime 4 + prefetch");
@@ -153,11 +155,11 @@ template <typename T, int S, int U>
 struct RingLds {
   T un[U][kNF][64];          // U^n rows, slot = loop trip mod U
   T uh[2 * S][kNF][64];      // U^{n+1/2} rows, slot = loop trip mod 2S
-  // C's per-lane FP64 accumulators of the written cells' sums and of the
-  // boundary ledger: kept in LDS, not in registers, through the whole march
-  // (each lane adds only to its own entries, in program order).
+  // C's per-lane FP64 accumulators of the written cells' sums and (FP64)
+  // of the boundary ledger: kept in LDS, not in registers, through the whole
+  // march (each lane adds only to its own entries, in program order).
   double sum[kNF][64];
-  double ledger[kNF][64];
+  double ledger[sizeof(T) == 8 ? kNF : 1][64];
 };
 
 template <typename T, int AXIS, int EOS>
@@ -281,6 +283,7 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
   using C = MarchCommon<T, AXIS, EOS>;
   T u[kNF][8], d[kNF][8], q2[kNF][8], hc[kNF][8], gc[kNF][8], ac[kNF][8];
   T ec[8], fE[8], fM[8], rd[8];
+  double led[kNF];   // boundary ledger when it is not kept in LDS
   __amdgpu_buffer_rsrc_t dst[kNF];
   int off_col, step_bytes;
 
@@ -344,8 +347,13 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       for (int q = 0; q < kNF; ++q) {
         const double f = (q == 0) ? double(fE[S3]) : ((q == QP) ? double(fM[S3]) : 0.0);
         const double F = face_flux(e64, double(u[q][S3]), this->lam, f);
-        if (left_edge) L.ledger[q][this->lane] -= F;
-        if (k == N - 1) L.ledger[q][this->lane] += F;
+        if constexpr (MarchCfg<T, EOS>::ledger_in_lds) {
+          if (left_edge) L.ledger[q][this->lane] -= F;
+          if (k == N - 1) L.ledger[q][this->lane] += F;
+        } else {
+          if (left_edge) led[q] -= F;
+          if (k == N - 1) led[q] += F;
+        }
       }
     }
     // ---- corrector of cell i-4 .. U^{n+1} of cell o = i-6
@@ -501,7 +509,8 @@ void sweep_march(SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
         L.sum[q][lane] = 0.0;
-        L.ledger[q][lane] = 0.0;
+        if constexpr (MarchCfg<T, EOS>::ledger_in_lds) L.ledger[q][lane] = 0.0;
+        else Cw.led[q] = 0.0;
       }
       // C at trip t handles P's iteration of trip t - kSync (cell
       // i_lo + t - kSync).  Its first kSync trips read ring slots P has not
@@ -530,7 +539,8 @@ void sweep_march(SweepArgs A) {
 #pragma unroll
         for (int q = 0; q < kNF; ++q) {
           acc[R_SUM + q] = L.sum[q][lane];
-          acc[R_LEDGER + q] = L.ledger[q][lane];
+          if constexpr (MarchCfg<T, EOS>::ledger_in_lds) acc[R_LEDGER + q] = L.ledger[q][lane];
+          else acc[R_LEDGER + q] = Cw.led[q];
         }
         acc[R_MAXEPS] = Cw.maxeps;
         acc[R_CLAMP] = double(Cw.n_clamp);
