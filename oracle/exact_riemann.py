@@ -1,6 +1,7 @@
 """Exact solution of the relativistic shock tube for p = e/3.
 
-Independent of the oracle and of the GPU path: written from the textbook
+TEST INFRASTRUCTURE ONLY (like the rest of this package).  Independent of the
+C oracle and of the GPU path: written from the textbook
 theory of the one-dimensional relativistic Riemann problem for an
 ultra-relativistic ideal gas (c_s^2 = 1/3), both states initially at rest,
 e_L > e_R.  The solution is a left-moving rarefaction, a contact and a

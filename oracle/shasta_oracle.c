@@ -33,8 +33,10 @@
  *   - the eigenframe recovery is a fixed-point iteration (Sec. 3, last
  *     paragraph) started at v0 = M/E, stopped when two iterates differ by at
  *     most 2^-50, at most 200 iterations; an admissibility guard
- *     E >= 1e-300, |M| <= (1 - 1e-10) E is applied inside the recovery only
- *     and counted, the conserved fields are never modified by it;
+ *     E >= 1e-300, |M| <= (1 - 1e-10) E (decided on the squares: |M|^2 >
+ *     ((1 - 1e-10) E)^2 clamps) is applied inside the recovery only and
+ *     counted once per interior cell and time level (n and n+1/2) of each
+ *     sweep; the conserved fields are never modified by it;
  *   - the velocity points along M (eq. cf-momentum);
  *   - the constant diff scales the phoenical antiflux (1 by default); the
  *     runs without antiflux are diff = 0 (Sec. 3.1, Sec. 4);
@@ -132,11 +134,15 @@ int orc_recover(const orc_eos* eos, double E, double Mx, double My, double Mz,
                 double R, double* e_out, double* p_out, double* v_out, double* vx,
                 double* vy, double* vz, int* iters_out, int* clamped,
                 int* floored) {
-  const double M = sqrt(Mx * Mx + (My * My + Mz * Mz));
+  const double M2 = Mx * Mx + (My * My + Mz * Mz);
+  const double M = sqrt(M2);
   double Ec = E, Mc = M;
   int fl = 0, cl = 0, conv = 1, it = 0;
   if (!(Ec >= ORC_E_FLOOR)) { Ec = ORC_E_FLOOR; fl = 1; }
-  if (Mc > ORC_M_FRAC * Ec) { Mc = ORC_M_FRAC * Ec; cl = 1; }
+  /* the guard compares squares, |M|^2 > ((1-1e-10) E)^2, so that the
+   * decision needs no square root */
+  const double Mmax = ORC_M_FRAC * Ec;
+  if (M2 > Mmax * Mmax) { Mc = Mmax; cl = 1; }
   double v = 0.0;
   if (Mc > 0.0) {
     v = Mc / Ec;
@@ -299,16 +305,19 @@ static void orc_sweep_pencil(const orc_eos* eos, int N, int axis, double lam,
   const int qt1 = 1 + (axis == 0 ? 1 : 0); /* the two transverse momenta */
   const int qt2 = 1 + (axis == 2 ? 1 : 2);
 
-  /* time level n: halo, then recovery on all N+6 cells */
+  /* time level n: halo, then recovery on all N+6 cells; guard activations
+   * and failures are counted on the N interior cells only (a halo cell
+   * repeats its edge cell) */
   for (int q = 0; q < ORC_NF; ++q) orc_fill_halo(N, u[q]);
   for (int i = 0; i < n; ++i) {
     double e, p, v, vel[3];
     int it, cl, fl;
+    const int interior = i >= ORC_HALO && i < ORC_HALO + N;
     if (!orc_recover(eos, u[0][i], u[qpar][i], u[qt1][i], u[qt2][i], u[4][i], &e, &p,
                      &v, &vel[0], &vel[1], &vel[2], &it, &cl, &fl))
-      cnt->noconv++;
-    cnt->clamp += cl;
-    cnt->floor += fl;
+      cnt->noconv += interior;
+    cnt->clamp += interior * cl;
+    cnt->floor += interior * fl;
     eps[i] = (0.5 * lam) * vel[0];
     fE[i] = p * vel[0];
     fM[i] = p;
@@ -324,11 +333,12 @@ static void orc_sweep_pencil(const orc_eos* eos, int N, int axis, double lam,
   for (int i = 0; i < n; ++i) {
     double e, p, v, vel[3];
     int it, cl, fl;
+    const int interior = i >= ORC_HALO && i < ORC_HALO + N;
     if (!orc_recover(eos, uh[0][i], uh[qpar][i], uh[qt1][i], uh[qt2][i], uh[4][i], &e,
                      &p, &v, &vel[0], &vel[1], &vel[2], &it, &cl, &fl))
-      cnt->noconv++;
-    cnt->clamp += cl;
-    cnt->floor += fl;
+      cnt->noconv += interior;
+    cnt->clamp += interior * cl;
+    cnt->floor += interior * fl;
     eps[i] = lam * vel[0];
     fE[i] = p * vel[0];
     fM[i] = p;

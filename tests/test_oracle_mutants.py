@@ -13,6 +13,7 @@ from paper_1206_0919_amd import inputs
 import test_oracle_fct as tf
 import test_oracle_physics as tp
 import test_oracle_recovery as tr
+import test_oracle_reductions as tq
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "shasta_oracle.c")
 
@@ -50,6 +51,14 @@ MUTANTS = {
                            "return eos->tp[k] + slope * (e - eos->te[k + 1]);"),
     "table_search_off_by_one": ("if (eos->te[mid] <= e) lo = mid; else hi = mid;",
                                 "if (eos->te[mid + 1] <= e) lo = mid; else hi = mid;"),
+    "sum_uncompensated": ("return s + c;", "return s;"),
+    "ledger_uncompensated": ("ledger[q] += s + c;", "ledger[q] += s;"),
+    "max_eps_from_predictor": ("if (fabs(eps[i]) > *maxeps) *maxeps = fabs(eps[i]);",
+                               "if (fabs(0.5 * eps[i]) > *maxeps) *maxeps = fabs(0.5 * eps[i]);"),
+    "guard_counts_halo": ("const int interior = i >= ORC_HALO && i < ORC_HALO + N;\n"
+                          "    if (!orc_recover(eos, u[0][i]",
+                          "const int interior = 1;\n    if (!orc_recover(eos, u[0][i]"),
+    "guard_without_margin": ("const double Mmax = ORC_M_FRAC * Ec;", "const double Mmax = Ec;"),
 }
 
 PINS = [
@@ -69,6 +78,13 @@ PINS = [
     lambda o, ob: tp.test_planar_invariance_bitwise(o),
     lambda o, ob: tp.test_conservation_ledger(o),
     lambda o, ob: tp.test_schedule_is_listing_2_table(o),
+    lambda o, ob: tp.test_uniform_flow_is_steady_through_outflow_faces(o),
+    lambda o, ob: tp.test_sweep_is_the_composition_of_its_parts(o),
+    lambda o, ob: tp.test_guard_counts_interior_cells_of_both_levels(o),
+    lambda o, ob: tr.test_guard_clamp_and_floor(o),
+    lambda o, ob: tq.test_sum_is_compensated(o),
+    lambda o, ob: tq.test_ledger_sum_over_pencils_is_compensated(o),
+    lambda o, ob: tq.test_max_eps_is_the_corrector_courant_number(o),
 ]
 
 
