@@ -1,13 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the relativistic SHASTA time step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--variants]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-legs] [--bag400]
+                    [--variants]
 
 A step is one full time step (three directional sweeps and the step
-reductions) of the whole batch, with the state resident in HBM.  Prints one
-JSON line with cell-updates/s, the roofline of the dominant kernel (HIP-event
-timing of each launch on the library's stream, algorithmic bytes per launch)
-and the FP64 CPU oracle timed on a bounded sample on the host cores.
+reductions) of the whole batch, with the state resident in HBM.  After W
+warm-up steps and one captured and replayed 6-step graph cycle, K steps are
+timed five times; the value is the median.  Prints one JSON line with
+cell-updates/s, the roofline of the dominant kernel (HIP-event timing of each
+launch on the library's stream, algorithmic bytes per launch), the FP32-mixed
+and batched legs of the metric (each with its throughput, roofline and field
+error against the FP64 path) and the FP64 CPU oracle timed on a bounded
+sample on the host cores.
 
 Workloads (synthetic, seeded):
   hotspots200     200^3, dx 0.2 fm, dt/dx 0.4, p = e/3, 64 Gaussian hot spots,
@@ -132,6 +137,17 @@ def make_state(torch, B, wl, precision):
     return s, prims, cells
 
 
+def warm_through_cycle(torch, s, dt, warmup):
+    """`warmup` steps, then on to the next multiple of 6 steps and one whole
+    6-step cycle: the step graph is captured and replayed before any timed
+    step (the timed steps reuse it: the buffer parity is the same at every
+    multiple of 6 steps)."""
+    s.step(dt, warmup)
+    k = s.step_index()
+    s.step(dt, (-k) % 6 + 6)
+    torch.cuda.synchronize()
+
+
 def time_steps(torch, s, dt, steps):
     st = s.stream
     a = torch.cuda.Event(enable_timing=True)
@@ -199,6 +215,84 @@ def cpu_baseline(wl, prims, budget_s=20.0):
                 host=dict(cpu=cpu, nproc=os.cpu_count()))
 
 
+def field_errors(torch, B, wl, prims, dec64, dec32, steps):
+    """Per-field max and L1 error of the FP32-mixed path against the FP64 path
+    on the GPU, after `steps` steps of the workload from its initial state
+    (max |d| / max |FP64|, for the momenta over all three components; L1 =
+    sum |d| / sum |FP64|), over all events of the batch."""
+    dims = wl["dims"] if isinstance(wl["dims"], list) else [wl["dims"]]
+    kind, params = wl["eos"]
+    eos = (B.EOS_BAG, params) if kind == "bag" else None
+    dt = wl["lam"] * wl["dx"]
+    out = {}
+    for prec, dec in ((B.FP64, dec64), (B.FP32_MIXED, dec32)):
+        s = B.Shasta(dims, wl["dx"], precision=prec, eos=eos)
+        if dec is not None:
+            s.set_decomposition(dec)
+        for k, pr in enumerate(prims):
+            s.write_primitive(k, *[torch.from_numpy(a) for a in pr.as_tuple()])
+        s.step(dt, steps)
+        out[prec] = s
+    names = ("E", "Mx", "My", "Mz", "R")
+    dmax = [0.0] * 5
+    rmax = [0.0] * 5
+    dsum = [0.0] * 5
+    rsum = [0.0] * 5
+    for k in range(len(dims)):
+        ref = out[B.FP64].read_conserved(k)
+        got = out[B.FP32_MIXED].read_conserved(k)
+        for q in range(5):
+            d = (got[q] - ref[q]).abs()
+            dmax[q] = max(dmax[q], d.max().item())
+            rmax[q] = max(rmax[q], ref[q].abs().max().item())
+            dsum[q] += d.sum().item()
+            rsum[q] += ref[q].abs().sum().item()
+    for s in out.values():
+        s.close()
+    mref = max(rmax[1:4])
+    res = {"steps": steps, "against": "GPU FP64 run of the same workload"}
+    for q in range(5):
+        den = mref if q in (1, 2, 3) else rmax[q]
+        res[names[q]] = {"max_rel": dmax[q] / den if den > 0 else dmax[q],
+                         "l1_rel": dsum[q] / rsum[q] if rsum[q] > 0 else dsum[q]}
+    return res
+
+
+def leg_record(torch, B, name, steps, warmup, autotune):
+    """One precision/batching leg of the metric: throughput, dominant-kernel
+    roofline and field error against FP64."""
+    s, prims, wl, cells, ms, prof, prec, reps = run_workload(torch, B, name, steps, warmup,
+                                                             autotune)
+    esize = 8 if prec == B.FP64 else 4
+    sw = {k: x for k, x in prof.items() if k.startswith("sweep") and x["launches"]}
+    dom = max(sw, key=lambda k: sw[k]["ms_total"])
+    per_launch = cells * FIELD_PASSES * esize
+    ach = per_launch / (sw[dom]["avg_us"] * 1e-6) / 1e9
+    dec = s.decomposition()
+    s.close()
+    log(f"{name}: measuring the field error against FP64 over {wl['steps']} steps")
+    err = field_errors(torch, B, wl, prims, None, dec, wl["steps"])
+    return {
+        "value": cells * steps / (ms / 1000.0), "unit": "cell-updates/s",
+        "ms_per_step": ms / steps, "steps": steps,
+        "repeats_ms_per_step": [r / steps for r in reps],
+        "dtype": "f32 fields, f64 recovery and sums" if prec == B.FP32_MIXED else "f64",
+        "config": {"workload": wl["name"],
+                   "grid": wl["dims"] if not isinstance(wl["dims"], list)
+                   else f"{len(wl['dims'])} events",
+                   "cells": cells, "dx_fm": wl["dx"], "dt_over_dx": wl["lam"],
+                   "eos": wl["eos"][0], "precision": wl["precision"]},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "kernel": dom,
+                     "kernel_avg_us": sw[dom]["avg_us"], "bytes_per_launch": per_launch,
+                     "note": "FP32 fields: the sweeps are bound by VALU issue (unpacked FP32 "
+                             "FCT, FP64 recoveries), not by HBM"},
+        "decomposition": format_tiles(dec),
+        "kernels": prof,
+        "error_vs_fp64": err,
+    }
+
+
 def parse_tiles(text):
     """'p0,p1,pers/p0,p1,pers/p0,p1,pers' (x/y/z) -> list of triples."""
     dec = [tuple(int(v) for v in part.split(",")) for part in text.split("/")]
@@ -228,15 +322,14 @@ def run_workload(torch, B, name, steps, warmup, autotune=True, profile_steps=12,
         s.autotune(dt, 4)
         log(f"{name}: autotuned in {time.time() - t0:.1f}s: "
             + format_tiles(s.decomposition()))
-    s.step(dt, warmup)
-    torch.cuda.synchronize()
-    log(f"{name}: warmup {warmup} steps done; timing {steps} steps")
-    ms = time_steps(torch, s, dt, steps)
-    # five more timed repetitions (a fifth of the steps each) for the spread
-    rsteps = max(20, steps // 5)
-    reps = [time_steps(torch, s, dt, rsteps) / rsteps for _ in range(5)]
+    warm_through_cycle(torch, s, dt, warmup)
+    log(f"{name}: warmup {warmup} steps and a captured 6-step cycle done; "
+        f"timing 5 x {steps} steps")
+    # five timed repetitions of exactly `steps` steps; the median is the value
+    reps = [time_steps(torch, s, dt, steps) for _ in range(5)]
+    ms = sorted(reps)[len(reps) // 2]
     prof = kernel_profile(torch, s, dt, profile_steps)
-    return s, prims, wl, cells, ms, prof, precision, (rsteps, reps)
+    return s, prims, wl, cells, ms, prof, precision, reps
 
 
 def main():
@@ -245,9 +338,12 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="hotspots200")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the FP32-mixed (shock256_mixed) and batched (batch96) legs")
+    ap.add_argument("--bag400", action="store_true",
+                    help="also measure the 400^3 bag-model leg")
     ap.add_argument("--variants", action="store_true",
-                    help="also measure the FP32 and batched workloads and the "
-                         "workload without antiflux")
+                    help="also measure the workload without antiflux")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tiles", default=None,
@@ -264,7 +360,7 @@ def main():
     from paper_1206_0919_amd import binding as B
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    s, prims, wl, cells, ms, prof, precision, (rsteps, reps) = run_workload(
+    s, prims, wl, cells, ms, prof, precision, reps = run_workload(
         torch, B, args.workload, args.steps, args.warmup, not args.no_autotune,
         tiles=parse_tiles(args.tiles) if args.tiles else None)
     value = cells * args.steps / (ms / 1000.0)
@@ -286,8 +382,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
-        "repeats": {"steps_each": rsteps, "ms_per_step": reps,
-                    "median_ms_per_step": sorted(reps)[len(reps) // 2]},
+        "repeats": {"steps_each": args.steps,
+                    "ms_per_step": [r / args.steps for r in reps],
+                    "value_is": "median of the five repetitions"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -310,33 +407,23 @@ def main():
     red = s.reduce(0)
     rec["check"] = {"nonfinite": red["nonfinite"], "clamp": red["clamp"],
                     "floor": red["floor"], "max_eps": red["max_eps"]}
+    if not args.no_legs:
+        rec["legs"] = {}
+        names = ["shock256_mixed", "batch96"] + (["bag400"] if args.bag400 else [])
+        for name in names:
+            rec["legs"][name] = leg_record(torch, B, name, args.steps, args.warmup,
+                                           not args.no_autotune)
     if args.variants:
-        rec["variants"] = {}
-        for name in ("shock256_mixed", "batch96"):
-            v = run_workload(torch, B, name, max(20, args.steps // 5), args.warmup,
-                             not args.no_autotune)
-            vs, _, vwl, vcells, vms, vprof, vprec, _ = v
-            vsteps = max(20, args.steps // 5)
-            vsw = {k: x for k, x in vprof.items() if k.startswith("sweep") and x["launches"]}
-            vdom = max(vsw, key=lambda k: vsw[k]["ms_total"])
-            vesize = 8 if vprec == B.FP64 else 4
-            vach = vcells * FIELD_PASSES * vesize / (vsw[vdom]["avg_us"] * 1e-6) / 1e9
-            rec["variants"][name] = {
-                "value": vcells * vsteps / (vms / 1000.0), "unit": "cell-updates/s",
-                "ms_per_step": vms / vsteps, "steps": vsteps, "cells": vcells,
-                "dominant_kernel": vdom, "achieved_GBs": vach,
-                "frac": vach / HBM_PEAK_GBS, "kernels": vprof}
-            vs.close()
         # the paper's runs without anti-flux: same workload, transport only;
         # the difference is the cost of the antiflux and its limiter
-        nsteps = max(20, args.steps // 5)
-        ns, _, _, ncells, nms, nprof, _, _ = run_workload(torch, B, args.workload, nsteps,
-                                                       args.warmup, not args.no_autotune,
-                                                       diff=0.0)
+        rec["variants"] = {}
+        ns, _, _, ncells, nms, nprof, _, _ = run_workload(torch, B, args.workload, args.steps,
+                                                          args.warmup, not args.no_autotune,
+                                                          diff=0.0)
         rec["variants"][args.workload + "_without_antiflux"] = {
-            "value": ncells * nsteps / (nms / 1000.0), "unit": "cell-updates/s",
-            "ms_per_step": nms / nsteps, "steps": nsteps,
-            "antiflux_share_of_step": 1.0 - (nms / nsteps) / rec["ms_per_step"],
+            "value": ncells * args.steps / (nms / 1000.0), "unit": "cell-updates/s",
+            "ms_per_step": nms / args.steps, "steps": args.steps,
+            "antiflux_share_of_step": 1.0 - (nms / args.steps) / rec["ms_per_step"],
             "kernels": nprof}
         ns.close()
     if not args.no_cpu_baseline:

@@ -103,9 +103,12 @@ int shasta_bind_workspace(shasta_t* h, void* dev_ptr, size_t bytes);
  * p_k >= 0, finite, every slope (p_{k+1} - p_k)/(e_{k+1} - e_k) in [0, 1];
  * p is linear between neighbouring nodes and the last segment continues
  * past e_{m-1}.  SHASTA_EOS_BARYON (the pressure from the rest-frame energy
- * and baryon densities, Sec. 3, last paragraph) takes params = {cs2, mass}:
- * p = cs2 max(0, e - mass n), 0 < cs2 <= 1, mass >= 0 in GeV; its recovery
- * solves for v with n = R sqrt(1 - v^2) (safeguarded Newton iteration).
+ * and baryon densities, Sec. 3, last paragraph) takes params = {cs2, mass}
+ * or {cs2, mass, iterations}: p = cs2 max(0, e - mass n), 0 < cs2 <= 1,
+ * mass >= 0 in GeV; its recovery solves for v with n = R sqrt(1 - v^2) by a
+ * safeguarded Newton iteration of at most `iterations` steps (an integer in
+ * [1, 64], 16 by default); a recovery still unconverged then keeps its last
+ * iterate and is counted (shasta_reduce counters[2], SHASTA_ENOCONVERGE).
  * EINVAL on any violation (the previous EOS stays).  May be called before or
  * after shasta_bind_workspace.  The tabled and baryon EOS always use the grid
  * launch (shasta_set_persistent is then ignored). */
@@ -144,8 +147,11 @@ int shasta_step(shasta_t* h, double dt_fm, int nsteps);
 
 /* Copy one field of event ev to dst_dev (dense FP64, the event's cells).
  * field 0..4: E, M_x, M_y, M_z, R; 5..10: e, p, v_x, v_y, v_z, n recomputed
- * from the conserved state.  Synchronizes; returns SHASTA_ENONFINITE if a
- * non-finite value was flagged since the last write. */
+ * from the conserved state.  Synchronizes; the field is copied in every case,
+ * but the call returns SHASTA_ENONFINITE if a non-finite value was flagged
+ * since the last write, else SHASTA_ENOCONVERGE if a recovery of the sweeps
+ * stopped before its root converged (baryon EOS only) since the last
+ * write_primitive. */
 int shasta_read_field(shasta_t* h, int ev, int field, double* dst_dev);
 
 /*
@@ -153,10 +159,16 @@ int shasta_read_field(shasta_t* h, int ev, int field, double* dst_dev);
  * cells of E, M_x, M_y, M_z, R after the last step; out[5..9]: accumulated
  * net boundary outflow of the same fields since the last write_primitive
  * (sum(t) + outflow = sum(0) is the conservation invariant); out[10]: largest
- * |lambda v_sweep| seen; out[11]: elapsed time t.  counters[0..3]: recoveries
- * with |M| clamped, with E floored, root solves not converged (always 0: the
- * device root solve is closed form), steps with non-finite values.
- * Sums are deterministic (fixed reduction order).
+ * |lambda v_sweep| of the corrector's half-step velocity (Sec. 3.1) seen;
+ * out[11]: elapsed time t.  counters[0..3]: recoveries with |M| clamped,
+ * recoveries with E floored (the admissibility guard of the recovery,
+ * Sec. 3, the relativistic correction), recoveries whose iterative root
+ * solve stopped before converging (baryon EOS only: the other EOS are solved
+ * in closed form), steps with non-finite values.  The guard and convergence
+ * counters count each interior cell once per time level (n and n+1/2) of
+ * every sweep.  Sums are deterministic (fixed reduction order).  The outputs
+ * are written in every case; the return value is SHASTA_ENONFINITE or
+ * SHASTA_ENOCONVERGE as for shasta_read_field.
  */
 int shasta_reduce(shasta_t* h, int ev, double out[12], int64_t counters[4]);
 
@@ -207,11 +219,22 @@ int shasta_get_persistent(const shasta_t* h, int axis, int* enable);
 int shasta_set_antidiffusion(shasta_t* h, double diff);
 
 /* Time candidate decompositions (tiles and persistent or not) on the device
- * with the given dt, keep the fastest per axis.  A candidate's time is the
- * fastest of three blocks of reps sweeps; the four fastest of the first pass
- * are timed again, interleaved, three more times.  The state is untouched (a
- * sweep writes only the second buffer).  Synchronous. */
+ * with the given dt and keep the fastest per axis.  First pass, per axis: a
+ * candidate's time is the fastest of three blocks of reps sweeps of that
+ * axis (each reads the current buffer and writes the other one); the six
+ * fastest are timed again, interleaved, three more times.  Second pass: the
+ * six fastest of each axis are timed in real time steps (three blocks of
+ * reps steps, the other axes at their current choice), and the fastest
+ * steps decide.  The state is left as it was: the current fields and the
+ * accumulators of every event go to host memory (allocated by the call)
+ * before the second pass and back after it, with the step index.  The choice
+ * is kept, for the rest of the process, under the device, precision, EOS
+ * kind, antiflux on or off and the grid sizes of the batch: a later call
+ * with the same key takes it without timing.  Synchronous. */
 int shasta_autotune(shasta_t* h, double dt_fm, int reps);
+
+/* Forget every decomposition shasta_autotune kept in this process. */
+int shasta_forget_tuning(void);
 
 /* Capture the steady-state step cycle (6 steps) in a HIP graph and replay it
  * (enable = 1, default) or launch kernels one by one (enable = 0). */
@@ -240,7 +263,8 @@ int shasta_selftest_math(const double* in_dev, double* out_dev, int n,
 
 /* Recovery self-check with the handle's EOS (Sec. 3, last paragraph: the
  * boost to the rest frame): for n cells, in_dev[5i..5i+4] = (E, M_x, M_y,
- * M_z, R) -> out_dev[4i..4i+3] = (e, p, |v|, clamped + 2 floored), computed
+ * M_z, R) -> out_dev[4i..4i+3] = (e, p, |v|, clamped + 2 floored + 4 not
+ * converged), computed
  * by the same device code the sweeps use.  Device pointers; needs a bound
  * workspace (the tabled EOS lives there); synchronous on the handle's
  * stream. */

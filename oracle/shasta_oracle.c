@@ -409,14 +409,19 @@ void orc_sweep(const orc_eos* eos, int nx, int ny, int nz, int axis,
           U[q][base + j * stride[axis]] = pen[q][ORC_HALO + j];
     }
     for (int q = 0; q < ORC_NF; ++q) free(pen[q]);
+    /* integer counters: the order of the additions does not matter */
 #ifdef _OPENMP
-#pragma omp critical
+#pragma omp atomic
 #endif
-    {
-      tot.clamp += cnt.clamp;
-      tot.floor += cnt.floor;
-      tot.noconv += cnt.noconv;
-    }
+    tot.clamp += cnt.clamp;
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+    tot.floor += cnt.floor;
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+    tot.noconv += cnt.noconv;
   }
   for (int q = 0; q < ORC_NF; ++q) {
     double s = 0.0, c = 0.0;

@@ -53,6 +53,7 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "shasta_get_persistent": ([_h, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "shasta_autotune": ([_h, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "shasta_forget_tuning": ([], ctypes.c_int),
     "shasta_set_antidiffusion": ([_h, ctypes.c_double], ctypes.c_int),
     "shasta_set_graph": ([_h, ctypes.c_int], ctypes.c_int),
     "shasta_set_profiling": ([_h, ctypes.c_int], ctypes.c_int),
@@ -184,7 +185,7 @@ class Shasta:
         res = dict(sums=list(out[0:5]), outflow=list(out[5:10]), max_eps=out[10],
                    t=out[11], clamp=cnt[0], floor=cnt[1], noconv=cnt[2],
                    nonfinite=cnt[3], status=st)
-        if st not in (OK, ENONFINITE):
+        if st not in (OK, ENONFINITE, ENOCONVERGE):
             _check(self.h, st)
         return res
 
@@ -240,6 +241,10 @@ class Shasta:
         n = (ctypes.c_int64 * 4)()
         _check(self.h, shasta_read_profile(self.h, ms, n))
         return list(ms), list(n)
+
+
+def forget_tuning():
+    _check(None, shasta_forget_tuning())
 
 
 def stream_copy(src, dst, nbytes, stream):

@@ -5,9 +5,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +47,10 @@ size_t sweep_args_size();
 
 namespace {
 
+// Baryon-dependent EOS: iterations of the root solve, default and limit.
+constexpr int kNewtonDefault = 16;
+constexpr int kNewtonLimit = 64;
+
 // Axis order of step k: the permutation table of Listing 2.
 const int kBranch[18] = {0, 1, 2, 0, 2, 1, 2, 0, 1, 2, 1, 0, 1, 2, 0, 1, 0, 2};
 
@@ -62,7 +70,7 @@ struct shasta_handle {
   int precision = 0;
   int bc = 0;
   hipStream_t stream = nullptr;
-  EosParams eos{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr};
+  EosParams eos{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr, kNewtonDefault, 0};
   std::vector<double> eos_tab;   // tabled EOS: the 4 m doubles of EosParams::tab
   double diff = 1.0;
 
@@ -442,7 +450,27 @@ hipEvent_t take_event(shasta_t* h) {
   return e;
 }
 
-int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStream_t st) {
+// Device scratch of the step: reduction records of the three sweeps of a
+// step, step-reduction partials, then the queue counters (4 ints) and one
+// reduction ticket per event.  Counters and tickets are zero between steps.
+struct StepScratch {
+  double* rec[3];
+  double* partial;
+  int* cnt;
+  bool may_allocate;   // per-kernel timing events may be created
+};
+
+StepScratch workspace_scratch(shasta_t* h) {
+  StepScratch sc;
+  for (int k = 0; k < 3; ++k) sc.rec[k] = dev_rec(h, k);
+  sc.partial = reinterpret_cast<double*>(h->ws + h->off_part);
+  sc.cnt = reinterpret_cast<int*>(h->ws + h->off_cnt);
+  sc.may_allocate = true;
+  return sc;
+}
+
+int launch_sweep(shasta_t* h, const StepScratch& sc, int axis, int parity, int slot, double lam,
+                 hipStream_t st) {
   SweepArgs a;
   a.ev = dev_events(h);
   a.items = dev_items(h, axis);
@@ -451,7 +479,7 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
   a.field_base = h->ws;
   a.lam = lam;
   a.diff = h->diff;
-  a.rec = dev_rec(h, slot);
+  a.rec = sc.rec[slot];
   a.xwin = reinterpret_cast<const int32_t*>(h->ws + h->off_xwin);
   a.eos = h->eos;
   a.counter = nullptr;
@@ -466,11 +494,11 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
     const int res = shasta_launch::resident(h->precision == SHASTA_FP32_MIXED, h->eos.kind, axis);
     if (res > 0 && res < grid) {
       grid = res;
-      a.counter = reinterpret_cast<int*>(h->ws + h->off_cnt) + slot;
+      a.counter = sc.cnt + slot;
       a.order = reinterpret_cast<const int*>(h->ws + h->off_order[axis]);
     }
   }
-  const bool prof = h->profiling && st == h->stream;
+  const bool prof = h->profiling && st == h->stream && sc.may_allocate;
   ProfRec pr{axis, nullptr, nullptr};
   if (prof) {
     pr.a = take_event(h);
@@ -487,16 +515,17 @@ int launch_sweep(shasta_t* h, int axis, int parity, int slot, double lam, hipStr
 }
 
 // One time step (three sweeps and the step reduction) enqueued on st.
-int enqueue_step(shasta_t* h, int64_t k, int& parity, double dt, hipStream_t st) {
+int enqueue_step(shasta_t* h, const StepScratch& sc, int64_t k, int& parity, double dt,
+                 hipStream_t st) {
   const double lam = dt / h->dx;
   const int* perm = &kBranch[3 * (int)(k % 6)];
   for (int w = 0; w < 3; ++w) {
-    int rc = launch_sweep(h, perm[w], parity, w, lam, st);
+    int rc = launch_sweep(h, sc, perm[w], parity, w, lam, st);
     if (rc) return rc;
     parity ^= 1;
   }
-  const double* rec[3] = {dev_rec(h, 0), dev_rec(h, 1), dev_rec(h, 2)};
-  const bool prof = h->profiling && st == h->stream;
+  const double* rec[3] = {sc.rec[0], sc.rec[1], sc.rec[2]};
+  const bool prof = h->profiling && st == h->stream && sc.may_allocate;
   ProfRec pr{3, nullptr, nullptr};
   if (prof) {
     pr.a = take_event(h);
@@ -504,11 +533,8 @@ int enqueue_step(shasta_t* h, int64_t k, int& parity, double dt, hipStream_t st)
     if (!pr.a || !pr.b) return fail(h, SHASTA_EHIP, "hipEventCreate failed");
     HIPCHECK(h, hipEventRecord(pr.a, st));
   }
-  int* cnt = reinterpret_cast<int*>(h->ws + h->off_cnt);
   HIPCHECK(h, shasta_launch::finalize(dev_events(h), h->n_events, h->fin_max, rec, perm,
-                                      dev_acc(h, 0), dt, cnt,
-                                      reinterpret_cast<double*>(h->ws + h->off_part), cnt + 4,
-                                      st));
+                                      dev_acc(h, 0), dt, sc.cnt, sc.partial, sc.cnt + 4, st));
   if (prof) {
     HIPCHECK(h, hipEventRecord(pr.b, st));
     h->prof.push_back(pr);
@@ -523,7 +549,9 @@ int capture_cycle(shasta_t* h, double dt) {
   HIPCHECK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   int parity = h->parity;
   int rc = SHASTA_OK;
-  for (int s = 0; s < 6 && rc == SHASTA_OK; ++s) rc = enqueue_step(h, s, parity, dt, h->cap_stream);
+  const StepScratch sc = workspace_scratch(h);
+  for (int s = 0; s < 6 && rc == SHASTA_OK; ++s)
+    rc = enqueue_step(h, sc, s, parity, dt, h->cap_stream);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (rc) {
@@ -555,6 +583,16 @@ int check_event(shasta_t* h, int ev) {
   return SHASTA_OK;
 }
 
+// Status from an event's accumulators: non-finite values first, then root
+// solves that did not converge, since the last write.
+int health(shasta_t* h, const double* a) {
+  if (a[A_NONFINITE] > 0) return fail(h, SHASTA_ENONFINITE, "non-finite values in the fields");
+  if (a[A_NOCONV] > 0)
+    return fail(h, SHASTA_ENOCONVERGE, std::to_string((long long)a[A_NOCONV]) +
+                                           " recoveries stopped before their root converged");
+  return SHASTA_OK;
+}
+
 int read_acc(shasta_t* h, int ev, double* a) {
   HIPCHECK(h, hipMemcpyAsync(a, dev_acc(h, ev), sizeof(double) * A_SIZE,
                              hipMemcpyDeviceToHost, h->stream));
@@ -568,6 +606,53 @@ int refresh_sums(shasta_t* h, int ev) {
                                   d.pitch, d.ncell,
                                   reinterpret_cast<double*>(h->ws + h->off_scratch),
                                   dev_acc(h, ev) + A_SUM, h->stream));
+  return SHASTA_OK;
+}
+
+// One axis' decomposition as the tuner handles it: x: windows per wave (p0);
+// y/z: segment length (p0) and lanes along x (p1); persistent launch or not.
+struct TuneChoice {
+  int p0, p1;
+  bool pers;
+  float ms;
+};
+
+void set_choice(shasta_t* h, int ax, const TuneChoice& c) {
+  if (ax == 0) {
+    h->xwin = c.p0;
+  } else {
+    h->seg[ax] = c.p0;
+    h->lanes[ax] = c.p1;
+  }
+  h->persistent[ax] = c.pers;
+}
+
+TuneChoice current_choice(const shasta_t* h, int ax) {
+  return ax == 0 ? TuneChoice{h->xwin, 0, h->persistent[0], 0.0f}
+                 : TuneChoice{h->seg[ax], h->lanes[ax], h->persistent[ax], 0.0f};
+}
+
+// Decompositions chosen by the tuner in this process, by device, precision,
+// scheme (EOS kind, with or without antiflux) and the grids of the batch.
+std::map<std::string, std::array<TuneChoice, 3>>& tune_cache() {
+  static std::map<std::string, std::array<TuneChoice, 3>> cache;
+  return cache;
+}
+std::mutex& tune_cache_lock() {
+  static std::mutex m;
+  return m;
+}
+
+int tune_key(shasta_t* h, std::string& key) {
+  int dev = 0;
+  HIPCHECK(h, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHECK(h, hipGetDeviceProperties(&prop, dev));
+  key = std::string(prop.gcnArchName) + "/" + std::to_string(prop.pciDomainID) + ":" +
+        std::to_string(prop.pciBusID) + ":" + std::to_string(prop.pciDeviceID) + "/p" +
+        std::to_string(h->precision) + "/e" + std::to_string(h->eos.kind) + "/a" +
+        std::to_string(h->diff == 0.0 ? 0 : 1) + "/";
+  for (int v : h->dims) key += std::to_string(v) + ",";
   return SHASTA_OK;
 }
 
@@ -643,13 +728,13 @@ int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params) {
   if (!h) return SHASTA_EINVAL;
   if (kind == SHASTA_EOS_IDEAL) {
     if (n_params != 0) return fail(h, SHASTA_EINVAL, "ideal EOS takes no parameters");
-    h->eos = EosParams{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr};
+    h->eos = EosParams{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr, kNewtonDefault, 0};
   } else if (kind == SHASTA_EOS_BAG) {
     if (n_params != 2 || !params) return fail(h, SHASTA_EINVAL, "bag EOS takes {B, e_H}");
     const double B = params[0], eH = params[1];
     if (!(B > 0.0) || !(eH > 0.0) || !std::isfinite(B) || !std::isfinite(eH))
       return fail(h, SHASTA_EINVAL, "bag EOS needs B > 0 and e_H > 0");
-    h->eos = EosParams{1, 0, B, eH, 0.0, 0.0, nullptr};
+    h->eos = EosParams{1, 0, B, eH, 0.0, 0.0, nullptr, kNewtonDefault, 0};
   } else if (kind == SHASTA_EOS_TABLE) {
     if (!params || n_params < 4 || n_params % 2 || n_params / 2 > kMaxEosNodes)
       return fail(h, SHASTA_EINVAL, "tabled EOS takes {e_0..e_m-1, p_0..p_m-1}, 2 <= m <= " +
@@ -677,14 +762,23 @@ int shasta_set_eos(shasta_t* h, int kind, const double* params, int n_params) {
     tab[3 * m - 1] = tab[3 * m - 2];   // the last segment continues past the last node
     tab[4 * m - 1] = tab[4 * m - 2];
     h->eos_tab.swap(tab);
-    h->eos = EosParams{2, m, 0.0, 0.0, 0.0, 0.0, nullptr};
+    h->eos = EosParams{2, m, 0.0, 0.0, 0.0, 0.0, nullptr, kNewtonDefault, 0};
     if (int rc = upload_eos(h)) return rc;
   } else if (kind == SHASTA_EOS_BARYON) {
-    if (n_params != 2 || !params) return fail(h, SHASTA_EINVAL, "baryon EOS takes {cs2, mass}");
+    if ((n_params != 2 && n_params != 3) || !params)
+      return fail(h, SHASTA_EINVAL, "baryon EOS takes {cs2, mass} or {cs2, mass, iterations}");
     const double cs2 = params[0], mass = params[1];
     if (!(cs2 > 0.0 && cs2 <= 1.0) || !(mass >= 0.0) || !std::isfinite(mass))
       return fail(h, SHASTA_EINVAL, "baryon EOS needs 0 < cs2 <= 1 and a finite mass >= 0");
-    h->eos = EosParams{3, 0, 0.0, 0.0, cs2, mass, nullptr};
+    int iters = kNewtonDefault;
+    if (n_params == 3) {
+      const double it = params[2];
+      if (!(it >= 1.0 && it <= kNewtonLimit) || it != std::floor(it))
+        return fail(h, SHASTA_EINVAL, "baryon EOS: iterations must be an integer in [1, " +
+                                          std::to_string(kNewtonLimit) + "]");
+      iters = (int)it;
+    }
+    h->eos = EosParams{3, 0, 0.0, 0.0, cs2, mass, nullptr, iters, 0};
   } else {
     return fail(h, SHASTA_EINVAL, "unknown EOS kind");
   }
@@ -767,7 +861,8 @@ int shasta_step(shasta_t* h, double dt_fm, int nsteps) {
       continue;
     }
     int parity = h->parity;
-    if (int rc = enqueue_step(h, h->step_index, parity, dt_fm, h->stream)) return rc;
+    if (int rc = enqueue_step(h, workspace_scratch(h), h->step_index, parity, dt_fm, h->stream))
+      return rc;
     h->parity = parity;
     h->step_index += 1;
     left -= 1;
@@ -787,8 +882,7 @@ int shasta_read_field(shasta_t* h, int ev, int field, double* dst) {
                                   h->stream));
   double a[A_SIZE];
   if (int rc = read_acc(h, ev, a)) return rc;
-  if (a[A_NONFINITE] > 0) return fail(h, SHASTA_ENONFINITE, "non-finite values in the fields");
-  return SHASTA_OK;
+  return health(h, a);
 }
 
 int shasta_reduce(shasta_t* h, int ev, double out[12], int64_t counters[4]) {
@@ -808,8 +902,7 @@ int shasta_reduce(shasta_t* h, int ev, double out[12], int64_t counters[4]) {
   counters[1] = (int64_t)a[A_FLOOR];
   counters[2] = (int64_t)a[A_NOCONV];
   counters[3] = (int64_t)a[A_NONFINITE];
-  if (a[A_NONFINITE] > 0) return fail(h, SHASTA_ENONFINITE, "non-finite values in the fields");
-  return SHASTA_OK;
+  return health(h, a);
 }
 
 int shasta_destroy(shasta_t* h) {
@@ -886,6 +979,20 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
   if (!(dt_fm > 0.0) || !(dt_fm / h->dx < 0.5)) return fail(h, SHASTA_EINVAL, "bad dt");
   if (reps < 1) reps = 1;
   if (int rc = check_ready(h)) return rc;
+  // a decomposition chosen before for the same device, precision, scheme
+  // and grids is taken again without timing
+  std::string key;
+  if (int rc = tune_key(h, key)) return rc;
+  {
+    std::lock_guard<std::mutex> g(tune_cache_lock());
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      for (int ax = 0; ax < 3; ++ax) set_choice(h, ax, it->second[ax]);
+      build_tables(h);
+      drop_graph(h);
+      return upload_tables(h);
+    }
+  }
   const double lam = dt_fm / h->dx;
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHECK(h, hipEventCreate(&a));
@@ -895,22 +1002,28 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
   int max_n = 0;
   for (int e = 0; e < h->n_events; ++e)
     for (int ax = 0; ax < 3; ++ax) max_n = std::max(max_n, h->dims[3 * e + ax]);
-  auto time_axis = [&](int ax, float& ms) -> int {
-    // a sweep reads buffer `parity` and writes the other one, so repeated
-    // sweeps leave the state untouched; the queue counter of slot 0 is reset
-    // before every launch (a step does that in its reduction)
-    for (int r = 0; r < 2; ++r) {
-      HIPCHECK(h, reset_counters(h, h->stream));
-      if (int rc = launch_sweep(h, ax, h->parity, 0, lam, h->stream)) return rc;
-    }
+  // A sweep reads buffer `parity` and writes the other one, so repeated
+  // sweeps leave the state untouched; the queue counter of a sweep's slot is
+  // reset before every launch (a step does that in its reduction).  `axes`
+  // lists the sweeps of one timed unit: one axis alone, or the three axes of
+  // a step (all reading the same buffer, in the order of the step).
+  auto time_sweeps = [&](const int* axes, int n_axes, float& ms) -> int {
+    const StepScratch sc = workspace_scratch(h);
+    auto unit = [&]() -> int {
+      for (int w = 0; w < n_axes; ++w) {
+        HIPCHECK(h, reset_counters(h, h->stream));
+        if (int rc = launch_sweep(h, sc, axes[w], h->parity, w, lam, h->stream)) return rc;
+      }
+      return SHASTA_OK;
+    };
+    for (int r = 0; r < 2; ++r)
+      if (int rc = unit()) return rc;
     // the fastest of three timed blocks: filters clock ramps and interference
     ms = 1e30f;
     for (int t = 0; t < 3; ++t) {
       HIPCHECK(h, hipEventRecord(a, h->stream));
-      for (int r = 0; r < reps; ++r) {
-        HIPCHECK(h, reset_counters(h, h->stream));
-        if (int rc = launch_sweep(h, ax, h->parity, 0, lam, h->stream)) return rc;
-      }
+      for (int r = 0; r < reps; ++r)
+        if (int rc = unit()) return rc;
       HIPCHECK(h, hipEventRecord(b, h->stream));
       HIPCHECK(h, hipEventSynchronize(b));
       float t_ms = 0.0f;
@@ -919,27 +1032,26 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
     }
     return SHASTA_OK;
   };
-  int rc = SHASTA_OK;
-  // A candidate decomposition of one axis: x: windows per wave (p0); y/z:
-  // segment length (p0) and lanes along x (p1); persistent launch or not.
-  struct Cand {
-    int p0, p1;
-    bool pers;
-    float ms;
-  };
-  auto apply = [&](int ax, const Cand& c) -> int {
-    if (ax == 0) {
-      h->xwin = c.p0;
-    } else {
-      h->seg[ax] = c.p0;
-      h->lanes[ax] = c.p1;
-    }
-    h->persistent[ax] = c.pers;
+  auto apply = [&](int ax, const TuneChoice& c) -> int {
+    set_choice(h, ax, c);
     build_tables(h);
     return upload_tables(h);
   };
+  // SHASTA_TUNE_LOG set: every timing goes to stderr
+  const bool log = std::getenv("SHASTA_TUNE_LOG") != nullptr;
+  auto report = [&](const char* pass, int ax, const TuneChoice& c, float ms) {
+    if (log)
+      std::fprintf(stderr, "shasta_autotune %s axis %d p0 %d p1 %d persistent %d: %.4f ms\n",
+                   pass, ax, c.p0, c.p1, c.pers ? 1 : 0, ms);
+  };
+  int rc = SHASTA_OK;
+  // first pass, per axis: every candidate decomposition (x: windows per
+  // wave; y/z: segment length and lanes along x; persistent launch or not)
+  // timed on repeated sweeps of that axis alone; then the six fastest again,
+  // interleaved, three more times (a candidate keeps its fastest time)
+  std::vector<TuneChoice> ranked[3];
   for (int ax = 0; ax < 3 && rc == SHASTA_OK; ++ax) {
-    std::vector<Cand> cands;
+    std::vector<TuneChoice> cands;
     for (int pers = 0; pers < 2; ++pers) {
       if (ax == 0) {
         for (int w : {2, 4, 6, 8, 12, 16, 24, 32}) cands.push_back({w, 0, pers != 0, 0.0f});
@@ -956,36 +1068,108 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
             if (L >= 16 || L >= max_n) cands.push_back({std::min(L, max_n), lx, pers != 0, 0.0f});
       }
     }
-    // first pass: every candidate once
-    for (Cand& c : cands) {
+    const int one[1] = {ax};
+    for (TuneChoice& c : cands) {
       if ((rc = apply(ax, c))) break;
-      if ((rc = time_axis(ax, c.ms))) break;
+      if ((rc = time_sweeps(one, 1, c.ms))) break;
+      report("sweep", ax, c, c.ms);
     }
     if (rc) break;
-    // second pass: the four fastest again, interleaved over three rounds;
-    // a candidate keeps its fastest time
     std::stable_sort(cands.begin(), cands.end(),
-                     [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    const size_t top = std::min<size_t>(4, cands.size());
+                     [](const TuneChoice& x, const TuneChoice& y) { return x.ms < y.ms; });
+    const size_t top = std::min<size_t>(6, cands.size());
     for (int round = 0; round < 3 && rc == SHASTA_OK; ++round)
       for (size_t i = 0; i < top; ++i) {
         float ms;
         if ((rc = apply(ax, cands[i]))) break;
-        if ((rc = time_axis(ax, ms))) break;
+        if ((rc = time_sweeps(one, 1, ms))) break;
+        report("sweep-again", ax, cands[i], ms);
         cands[i].ms = std::min(cands[i].ms, ms);
       }
     if (rc) break;
-    size_t best = 0;
-    for (size_t i = 1; i < top; ++i)
-      if (cands[i].ms < cands[best].ms) best = i;
-    Cand c = cands[best];
-    if (ax == 0) {
-      h->xwin = c.p0;
-    } else {
-      h->seg[ax] = c.p0;
-      h->lanes[ax] = c.p1;
+    std::stable_sort(cands.begin(), cands.begin() + top,
+                     [](const TuneChoice& x, const TuneChoice& y) { return x.ms < y.ms; });
+    cands.resize(top);
+    ranked[ax] = cands;
+    set_choice(h, ax, cands[0]);
+  }
+  // second pass: a sweep alone, repeated on the same input, does not see
+  // what the step's other sweeps leave in the caches, nor their order of
+  // reading and writing.  The six fastest of each axis are timed again in
+  // real time steps (the other axes at their current choice), and the
+  // fastest step wins.  The steps advance the state, so the current buffer
+  // of every event, its accumulators, the step index and the buffer parity
+  // are kept in host memory and put back afterwards.
+  if (rc == SHASTA_OK) {
+    std::vector<char> saved;
+    const int parity0 = h->parity;
+    const int64_t step0 = h->step_index;
+    size_t total = sizeof(double) * A_SIZE * (size_t)h->n_events;
+    for (int e = 0; e < h->n_events; ++e) total += kNF * (size_t)h->evd[e].pitch * h->elem;
+    saved.resize(total);
+    auto copy_state = [&](bool back) -> int {
+      size_t o = 0;
+      for (int e = 0; e < h->n_events; ++e) {
+        const size_t n = kNF * (size_t)h->evd[e].pitch * h->elem;
+        char* dev = dev_field(h, e, parity0);
+        HIPCHECK(h, back ? hipMemcpyAsync(dev, saved.data() + o, n, hipMemcpyHostToDevice,
+                                          h->stream)
+                         : hipMemcpyAsync(saved.data() + o, dev, n, hipMemcpyDeviceToHost,
+                                          h->stream));
+        o += n;
+      }
+      const size_t n = sizeof(double) * A_SIZE * (size_t)h->n_events;
+      HIPCHECK(h, back ? hipMemcpyAsync(dev_acc(h, 0), saved.data() + o, n,
+                                        hipMemcpyHostToDevice, h->stream)
+                       : hipMemcpyAsync(saved.data() + o, dev_acc(h, 0), n,
+                                        hipMemcpyDeviceToHost, h->stream));
+      HIPCHECK(h, hipStreamSynchronize(h->stream));
+      return SHASTA_OK;
+    };
+    auto time_steps = [&](float& ms) -> int {
+      const StepScratch sc = workspace_scratch(h);
+      auto steps = [&](int n) -> int {
+        for (int k = 0; k < n; ++k) {
+          int parity = h->parity;
+          if (int r = enqueue_step(h, sc, h->step_index, parity, dt_fm, h->stream)) return r;
+          h->parity = parity;
+          h->step_index += 1;
+        }
+        return SHASTA_OK;
+      };
+      if (int r = steps(1)) return r;
+      ms = 1e30f;
+      for (int t = 0; t < 3; ++t) {
+        HIPCHECK(h, hipEventRecord(a, h->stream));
+        if (int r = steps(reps)) return r;
+        HIPCHECK(h, hipEventRecord(b, h->stream));
+        HIPCHECK(h, hipEventSynchronize(b));
+        float t_ms = 0.0f;
+        HIPCHECK(h, hipEventElapsedTime(&t_ms, a, b));
+        ms = std::min(ms, t_ms);
+      }
+      return SHASTA_OK;
+    };
+    rc = copy_state(false);
+    for (int ax = 0; ax < 3 && rc == SHASTA_OK; ++ax) {
+      const size_t n = std::min<size_t>(6, ranked[ax].size());
+      std::vector<float> best(n, 1e30f);
+      for (int round = 0; round < 2 && rc == SHASTA_OK; ++round)
+        for (size_t i = 0; i < n; ++i) {
+          float ms;
+          if ((rc = apply(ax, ranked[ax][i]))) break;
+          if ((rc = time_steps(ms))) break;
+          report("step", ax, ranked[ax][i], ms);
+          best[i] = std::min(best[i], ms);
+        }
+      if (rc) break;
+      const size_t w = std::min_element(best.begin(), best.end()) - best.begin();
+      set_choice(h, ax, ranked[ax][w]);
     }
-    h->persistent[ax] = c.pers;
+    h->parity = parity0;
+    h->step_index = step0;
+    const int rc_restore = copy_state(true);
+    if (rc == SHASTA_OK) rc = rc_restore;
   }
   build_tables(h);
   int rc2 = upload_tables(h);
@@ -993,7 +1177,19 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
   (void)hipEventDestroy(b);
   h->profiling = saved_prof;
   drop_graph(h);
+  if (rc == SHASTA_OK && rc2 == SHASTA_OK) {
+    std::array<TuneChoice, 3> c;
+    for (int ax = 0; ax < 3; ++ax) c[ax] = current_choice(h, ax);
+    std::lock_guard<std::mutex> g(tune_cache_lock());
+    tune_cache()[key] = c;
+  }
   return rc ? rc : rc2;
+}
+
+int shasta_forget_tuning(void) {
+  std::lock_guard<std::mutex> g(tune_cache_lock());
+  tune_cache().clear();
+  return SHASTA_OK;
 }
 
 int shasta_set_antidiffusion(shasta_t* h, double diff) {

@@ -22,6 +22,8 @@ enum : int {
   R_MAXEPS = 10,  // largest |lambda v| of the corrector
   R_CLAMP = 11,   // recoveries with |M| clamped
   R_FLOOR = 12,   // recoveries with E floored
+  R_NOCONV = 13,  // recoveries whose iterative root solve did not converge
+  R_USED = 14,    // entries of a record that are written
   R_SIZE = 16
 };
 
@@ -56,7 +58,7 @@ struct EventDesc {
 };
 
 // Step reduction: one block reduces kFinChunk records to one partial of
-// R_SIZE doubles (the 13 record entries, then the non-finite probe).
+// R_SIZE doubles (the R_USED record entries, then the non-finite probe).
 constexpr int kFinChunk = 256;
 
 constexpr int kFlatLanes = 1;      // y/z: lane layout of flattened columns
@@ -80,6 +82,7 @@ struct Item {
 
 constexpr int kMaxEosNodes = 1024;   // tabled EOS: most nodes
 
+
 struct EosParams {
   int32_t kind;  // 0 ideal, 1 bag, 2 table, 3 baryon-dependent
   int32_t n;     // table: nodes m
@@ -91,6 +94,8 @@ struct EosParams {
   // slope a_k and intercept b_k of segment k = [e_k, e_k+1] (p = a e + b;
   // entry m-1 repeats segment m-2, which continues past the last node)
   const double* tab;
+  int32_t newton_max;  // baryon: most iterations of the root solve
+  int32_t pad;
 };
 
 // Kernel arguments of one sweep (built by the host library).

@@ -49,14 +49,14 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// acc[0..4] sums, [5..9] ledger, [10] max eps, [11] clamp, [12] floor.
-// One record per work item (at the item's record index), written by lane 0:
-// deterministic (fixed butterfly) and independent of which block or wave
-// processed the item.
-__device__ __forceinline__ void wave_record(const double (&acc)[13], double* rec, int item) {
+// acc[0..4] sums, [5..9] ledger, [10] max eps, [11] clamp, [12] floor,
+// [13] root solves not converged.  One record per work item (at the item's
+// record index), written by lane 0: deterministic (fixed butterfly) and
+// independent of which block or wave processed the item.
+__device__ __forceinline__ void wave_record(const double (&acc)[R_USED], double* rec, int item) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int j = 0; j < 13; ++j) {
+  for (int j = 0; j < R_USED; ++j) {
     const double v = (j == R_MAXEPS) ? wave_max(acc[j]) : wave_sum(acc[j]);
     if (lane == 0) rec[(size_t)item * R_SIZE + j] = v;
   }
@@ -171,8 +171,10 @@ struct MarchCommon {
   bool active;
   const EosParams* eos;
   double lam, lamh;
-  T lamsrc, diff8;
+  T lamsrc;
+  Antidiff<T> ad;         // scales of the phoenical antiflux
   int n_clamp, n_floor;   // recoveries guarded, cells of the segment only
+  int n_noconv;           // root solves not converged, cells of the segment only
   double maxeps;          // C only
 };
 
@@ -240,6 +242,7 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
       if (this->active && (!EDGE || (i >= this->s0 && i < this->s1))) {
         this->n_clamp += r.clamped;
         this->n_floor += r.floored;
+        this->n_noconv += r.noconv;
       }
     }
     rd[S0] = interface_rcp(ep[S1], ep[S0]);
@@ -270,7 +273,7 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
       gp[q][S2] = hp[q][S1] - hp[q][S2];                                 // hat Delta_{i-2}
       const T sec = second_difference(d2, d4, d3);                       // at i-3
       if constexpr (antiflux_of<EOS>)
-        ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], sec, this->diff8);
+        ap[q][S3] = limited_antiflux(gp[q][S4], gp[q][S3], gp[q][S2], sec, this->ad);
       else
         ap[q][S3] = T(0);
       L.uh[hslot][q][this->lane] = update(hp[q][S3], ap[q][S3], ap[q][S4]);  // U^{n+1/2}_{i-3}
@@ -330,6 +333,7 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       if (this->active && (!EDGE || (k >= this->s0 && k < this->s1))) {
         this->n_clamp += r.clamped;
         this->n_floor += r.floored;
+        this->n_noconv += r.noconv;
         this->maxeps = fmax(this->maxeps, fabs(double(ec[S3])));
       }
     }
@@ -371,7 +375,7 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
       if (EDGE && left_edge) hc[q][S5] = hc[q][S4];                      // halo: hat U_{-2}
       gc[q][S5] = hc[q][S4] - hc[q][S5];                                 // hat Delta_{i-5}
       if constexpr (antiflux_of<EOS>)
-        ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], this->diff8);
+        ac[q][S6] = limited_antiflux(gc[q][S7], gc[q][S6], gc[q][S5], q2[q][S6], this->ad);
       else
         ac[q][S6] = T(0);
       const T out = update(hc[q][S6], ac[q][S6], ac[q][S7]);            // U^{n+1}_{i-6}
@@ -416,11 +420,12 @@ __device__ __forceinline__ void march_setup(M& m, const SweepArgs& A, const Item
   m.eos = &A.eos;
   m.lam = A.lam;
   m.lamh = 0.5 * A.lam;
-  m.diff8 = TT(A.diff * 0.125);
+  m.ad = antidiff_scales<TT>(A.diff);
   m.s0 = it.s0;
   m.s1 = it.s1;
   m.n_clamp = 0;
   m.n_floor = 0;
+  m.n_noconv = 0;
   m.maxeps = 0.0;
 }
 
@@ -441,9 +446,9 @@ void sweep_march(SweepArgs A) {
   // wave-uniform: keeps the work item and the buffer descriptors scalar
   const int item = __builtin_amdgcn_readfirstlane(item_at(A, k));
   const Item it = A.items[item];
-  double acc[13];
+  double acc[R_USED];
 #pragma unroll
-  for (int j = 0; j < 13; ++j) acc[j] = 0.0;
+  for (int j = 0; j < R_USED; ++j) acc[j] = 0.0;
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
     const int64_t fbytes = ev.ncell * (int64_t)sizeof(T);
@@ -491,6 +496,7 @@ void sweep_march(SweepArgs A) {
 #undef SHASTA_P
       acc[R_CLAMP] = P.active ? double(P.n_clamp) : 0.0;
       acc[R_FLOOR] = P.active ? double(P.n_floor) : 0.0;
+      acc[R_NOCONV] = P.active ? double(P.n_noconv) : 0.0;
     } else {
       MarchC<T, AXIS, EOS> Cw;
       // FP64 ideal gas (a barrier every trip): the consumer issues ahead of
@@ -545,19 +551,20 @@ void sweep_march(SweepArgs A) {
         acc[R_MAXEPS] = Cw.maxeps;
         acc[R_CLAMP] = double(Cw.n_clamp);
         acc[R_FLOOR] = double(Cw.n_floor);
+        acc[R_NOCONV] = double(Cw.n_noconv);
       }
     }
   }
   // one record per item: consumer and producer parts summed in a fixed order
   {
-    double v[13];
+    double v[R_USED];
 #pragma unroll
-    for (int j = 0; j < 13; ++j) v[j] = (j == R_MAXEPS) ? wave_max(acc[j]) : wave_sum(acc[j]);
+    for (int j = 0; j < R_USED; ++j) v[j] = (j == R_MAXEPS) ? wave_max(acc[j]) : wave_sum(acc[j]);
     if (wave == 1 && lane == 0)
-      for (int j = 0; j < 13; ++j) part[j] = v[j];
+      for (int j = 0; j < R_USED; ++j) part[j] = v[j];
     __syncthreads();
     if (wave == 0 && lane == 0) {
-      for (int j = 0; j < 13; ++j)
+      for (int j = 0; j < R_USED; ++j)
         A.rec[(size_t)it.rec * R_SIZE + j] = (j == R_MAXEPS) ? fmax(v[j], part[j]) : v[j] + part[j];
       if (PERSIST) next = atomicAdd(A.counter, 1) + (int)gridDim.x;
     }
@@ -640,21 +647,38 @@ __device__ __forceinline__ void x_coefficients(const T (&eps)[kXCells], const T 
   }
 }
 
-// One 1-D SHASTA application to the 4 owned positions of one field.
-// u: U^n; ul, ur, ur2: U^n at p-1, p+1, p+2.  AF = false: transport only.
+// Differences of U^n around the owned positions p of one field: dl =
+// Delta_{p-1}, dr = Delta_p = U_{p+1} - U_p, dn = Delta_{p+1}.  Each Delta is
+// formed once, by the lane owning its left cell, and the neighbours' values
+// arrive by DPP shifts (three per lane, as for the neighbouring U^n values).
+template <typename T>
+__device__ __forceinline__ void x_differences(const T (&u)[kXCells], T (&dl)[kXCells],
+                                              T (&dr)[kXCells], T (&dn)[kXCells]) {
+  const T next = from_right(u[0]);   // U^n of the first position of the next lane
+#pragma unroll
+  for (int j = 0; j < kXCells; ++j) dr[j] = ((j < kXCells - 1) ? u[j + 1] : next) - u[j];
+  const T dl0 = from_left(dr[kXCells - 1]);
+  const T dnl = from_right(dr[0]);
+#pragma unroll
+  for (int j = 0; j < kXCells; ++j) {
+    dl[j] = (j > 0) ? dr[j - 1] : dl0;
+    dn[j] = (j < kXCells - 1) ? dr[j + 1] : dnl;
+  }
+}
+
+// One 1-D SHASTA application to the owned positions of one field.
+// u: U^n; dl, dr, dn: its differences (x_differences).  AF = false:
+// transport only.
 template <bool AF, typename T>
-__device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCells],
-                                      const T (&ur)[kXCells], const T (&ur2)[kXCells],
+__device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&dl)[kXCells],
+                                      const T (&dr)[kXCells], const T (&dn)[kXCells],
                                       const Coef<T> (&k)[kXCells], const T (&s)[kXCells],
-                                      T diff8, T (&out)[kXCells]) {
+                                      const Antidiff<T>& ad, T (&out)[kXCells]) {
   T uh[kXCells], sec[kXCells];
 #pragma unroll
   for (int j = 0; j < kXCells; ++j) {
-    const T dr = ur[j] - u[j];       // Delta_p
-    const T dl = u[j] - ul[j];       // Delta_{p-1}
-    const T dn = ur2[j] - ur[j];     // Delta_{p+1}
-    sec[j] = second_difference(dn, dl, dr);
-    uh[j] = transport(k[j], s[j], dr, dl, u[j]);
+    sec[j] = second_difference(dn[j], dl[j], dr[j]);
+    uh[j] = transport(k[j], s[j], dr[j], dl[j], u[j]);
   }
   if constexpr (!AF) {
 #pragma unroll
@@ -672,7 +696,7 @@ __device__ __forceinline__ void x_fct(const T (&u)[kXCells], const T (&ul)[kXCel
   T a[kXCells];
 #pragma unroll
   for (int j = 0; j < kXCells; ++j)
-    a[j] = limited_antiflux(dhl[j], dh[j], dhr[j], sec[j], diff8);
+    a[j] = limited_antiflux(dhl[j], dh[j], dhr[j], sec[j], ad);
   const T al = from_left(a[kXCells - 1]);
 #pragma unroll
   for (int j = 0; j < kXCells; ++j) out[j] = update(uh[j], a[j], (j > 0) ? a[j - 1] : al);
@@ -701,7 +725,7 @@ void sweep_x(SweepArgs A) {
 #pragma unroll
   for (int j = 0; j < 10; ++j) acc10[j][lane] = 0.0;
   double maxeps = 0.0;
-  int n_clamp = 0, n_floor = 0;
+  int n_clamp = 0, n_floor = 0, n_noconv = 0;
   if (it.ev >= 0) {
     const EventDesc& ev = A.ev[it.ev];
     const int nx = ev.n[0];
@@ -718,7 +742,7 @@ void sweep_x(SweepArgs A) {
     const double lamh = 0.5 * lam;
     const T lamsrc_p = T(-0.25 * lam);
     const T lamsrc_c = T(-0.5 * lam);
-    const T diff8 = T(A.diff * 0.125);
+    const Antidiff<T> ad = antidiff_scales<T>(A.diff);
     T* hE = halo[wave][0];
     T* hF = halo[wave][1];
     T* hG = halo[wave][2];
@@ -789,22 +813,10 @@ void sweep_x(SweepArgs A) {
         fM[j] = T(r.p);
         n_clamp += out_ok[j] & (r.clamped != 0);
         n_floor += out_ok[j] & (r.floored != 0);
+        n_noconv += out_ok[j] & (r.noconv != 0);
       }
-      // ---- U^n neighbours p-1, p+1, p+2 of field q from the adjacent lanes
-      //      (taken again for the corrector rather than kept in registers)
-      auto neighbours = [&](int q, T (&ul)[kXCells], T (&ur)[kXCells], T (&ur2)[kXCells]) {
-        const T b_l = from_left(u[q][kXCells - 1]);
-        const T b_r0 = from_right(u[q][0]);
-        // position of the right neighbour lane's second slot, or, with one
-        // position per lane, of the lane two to the right
-        const T b_r1 = from_right(kXCells > 1 ? u[q][1 % kXCells] : b_r0);
-#pragma unroll
-        for (int j = 0; j < kXCells; ++j) {
-          ul[j] = (j > 0) ? u[q][j - 1] : b_l;
-          ur[j] = (j < kXCells - 1) ? u[q][j + 1] : b_r0;
-          ur2[j] = (j < kXCells - 2) ? u[q][j + 2] : ((j == kXCells - 2) ? b_r0 : b_r1);
-        }
-      };
+      // ---- the differences of U^n of field q are formed again for the
+      //      corrector rather than kept in registers (x_differences)
       // ---- predictor (lambda/2)
       Coef<T> k[kXCells];
       T sE[kXCells], sM[kXCells];
@@ -812,11 +824,11 @@ void sweep_x(SweepArgs A) {
       T uh[kNF][kXCells];
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
-        T ul[kXCells], ur[kXCells], ur2[kXCells], s[kXCells];
-        neighbours(q, ul, ur, ur2);
+        T dl[kXCells], dr[kXCells], dn[kXCells], s[kXCells];
+        x_differences(u[q], dl, dr, dn);
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
-        x_fct<antiflux_of<EOS>>(u[q], ul, ur, ur2, k, s, diff8, uh[q]);
+        x_fct<antiflux_of<EOS>>(u[q], dl, dr, dn, k, s, ad, uh[q]);
       }
       // ---- recovery at U^{n+1/2}; halo positions take their edge cell's
       //      values (through the wave's LDS table)
@@ -832,6 +844,7 @@ void sweep_x(SweepArgs A) {
         fMc[j] = T(r.p);
         n_clamp += out_ok[j] & (r.clamped != 0);
         n_floor += out_ok[j] & (r.floored != 0);
+        n_noconv += out_ok[j] & (r.noconv != 0);
         maxeps = out_ok[j] ? fmax(maxeps, fabs(double(ec[j]))) : maxeps;
         // table entry of position p at (p % kXCells) * 64 + p / kXCells:
         // a wave's writes and own-position reads touch distinct banks
@@ -860,11 +873,11 @@ void sweep_x(SweepArgs A) {
       x_coefficients(ec, fEc, fMc, lamsrc_c, k, sE, sM);
 #pragma unroll
       for (int q = 0; q < kNF; ++q) {
-        T ul[kXCells], ur[kXCells], ur2[kXCells], s[kXCells], out[kXCells];
-        neighbours(q, ul, ur, ur2);
+        T dl[kXCells], dr[kXCells], dn[kXCells], s[kXCells], out[kXCells];
+        x_differences(u[q], dl, dr, dn);
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) s[j] = (q == 0) ? sE[j] : ((q == QP) ? sM[j] : T(0));
-        x_fct<antiflux_of<EOS>>(u[q], ul, ur, ur2, k, s, diff8, out);
+        x_fct<antiflux_of<EOS>>(u[q], dl, dr, dn, k, s, ad, out);
         double sum = acc10[R_SUM + q][lane];
 #pragma unroll
         for (int j = 0; j < kXCells; ++j) {
@@ -891,12 +904,13 @@ void sweep_x(SweepArgs A) {
       }
     }
   }
-  double acc[13];
+  double acc[R_USED];
 #pragma unroll
   for (int j = 0; j < 10; ++j) acc[j] = acc10[j][lane];
   acc[R_MAXEPS] = maxeps;
   acc[R_CLAMP] = double(n_clamp);
   acc[R_FLOOR] = double(n_floor);
+  acc[R_NOCONV] = double(n_noconv);
   wave_record(acc, A.rec, it.rec);
   if (!PERSIST) break;
   int nk = 0;

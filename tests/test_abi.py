@@ -99,6 +99,11 @@ def test_state_and_eos_validation(b):
     for bad_b in ([0.0, 0.9], [1.2, 0.9], [0.3, -1.0], [0.3, float("inf")], [0.3]):
         assert b.shasta_set_eos(h, 3, *table(bad_b)) == b.EINVAL, bad_b
     assert b.shasta_set_eos(h, 3, *table([1.0 / 3.0, 0.938])) == b.OK
+    # {cs2, mass, iterations}: an integer cap of the root solve in [1, 64]
+    for bad_it in (0.0, 65.0, 2.5, -1.0, float("nan")):
+        assert b.shasta_set_eos(h, 3, *table([1.0 / 3.0, 0.938, bad_it])) == b.EINVAL, bad_it
+    for it in (1.0, 16.0, 64.0):
+        assert b.shasta_set_eos(h, 3, *table([1.0 / 3.0, 0.938, it])) == b.OK
     big = [float(k) for k in range(1025)] + [k / 3.0 for k in range(1025)]
     assert b.shasta_set_eos(h, 2, *table(big)) == b.EINVAL           # more than 1024 nodes
     assert b.shasta_set_eos(h, 0, None, 0) == b.OK
@@ -120,3 +125,5 @@ def test_state_and_eos_validation(b):
     assert b.shasta_read_field(h, 0, 11, None) == b.EINVAL
     assert b.shasta_destroy(h) == b.OK
     assert b.shasta_status_str(b.ENONFINITE) == b"non-finite value in the fields"
+    assert b.shasta_status_str(b.ENOCONVERGE) == b"recovery did not converge"
+    assert b.shasta_forget_tuning() == b.OK
