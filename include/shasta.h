@@ -145,6 +145,25 @@ int shasta_get_step_index(const shasta_t* h, int64_t* k);
  */
 int shasta_step(shasta_t* h, double dt_fm, int nsteps);
 
+/*
+ * shasta_step without any allocation, for callers that cannot allocate
+ * device memory or create runtime objects while it runs (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid it).  Same
+ * arguments, requirements and results as shasta_step, bit for bit; the
+ * fields and accumulators stay in the bound workspace, while the step's
+ * scratch (reduction records, step-reduction partials, queue counters,
+ * tickets) lives in a static device array of 16 MiB that the library holds
+ * on each GPU until the process ends.  Kernels are launched one by one (no
+ * graph, no timing events, no stream creation).  SHASTA_EINVAL, with nothing
+ * launched, if the current work tables need more scratch than that (the
+ * message gives both sizes; more x windows per work item, shasta_set_tiles,
+ * or fewer events reduce it).  All calls on one GPU share the array: calls
+ * that overlap on one GPU (other streams or threads) race.  The first call on
+ * a device looks up the array's device address (with that device current).
+ * Asynchronous on the stream.
+ */
+int shasta_step_noalloc(shasta_t* h, double dt_fm, int nsteps);
+
 /* Copy one field of event ev to dst_dev (dense FP64, the event's cells).
  * field 0..4: E, M_x, M_y, M_z, R; 5..10: e, p, v_x, v_y, v_z, n recomputed
  * from the conserved state.  Synchronizes; the field is copied in every case,

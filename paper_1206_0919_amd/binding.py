@@ -42,6 +42,7 @@ _SIGS = {
     "shasta_set_step_index": ([_h, ctypes.c_int64], ctypes.c_int),
     "shasta_get_step_index": ([_h, _i64p], ctypes.c_int),
     "shasta_step": ([_h, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "shasta_step_noalloc": ([_h, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "shasta_read_field": ([_h, ctypes.c_int, ctypes.c_int, _vp], ctypes.c_int),
     "shasta_reduce": ([_h, ctypes.c_int, _dp, _i64p], ctypes.c_int),
     "shasta_destroy": ([_h], ctypes.c_int),
@@ -159,6 +160,9 @@ class Shasta:
 
     def step(self, dt, nsteps=1):
         _check(self.h, shasta_step(self.h, float(dt), int(nsteps)))
+
+    def step_noalloc(self, dt, nsteps=1):
+        _check(self.h, shasta_step_noalloc(self.h, float(dt), int(nsteps)))
 
     def set_step_index(self, k):
         _check(self.h, shasta_set_step_index(self.h, int(k)))

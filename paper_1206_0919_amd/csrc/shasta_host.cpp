@@ -43,6 +43,7 @@ hipError_t sums(int fp32, const void* in, int64_t pitch, int64_t ncell, double* 
                 double* out, hipStream_t st);
 int sum_scratch_doubles();
 size_t sweep_args_size();
+hipError_t static_scratch(void** ptr);
 }  // namespace shasta_launch
 
 namespace {
@@ -866,6 +867,50 @@ int shasta_step(shasta_t* h, double dt_fm, int nsteps) {
     h->parity = parity;
     h->step_index += 1;
     left -= 1;
+  }
+  return SHASTA_OK;
+}
+
+int shasta_step_noalloc(shasta_t* h, double dt_fm, int nsteps) {
+  if (!h) return SHASTA_EINVAL;
+  if (!(dt_fm > 0.0) || !std::isfinite(dt_fm)) return fail(h, SHASTA_EINVAL, "dt must be > 0");
+  const double lam = dt_fm / h->dx;
+  if (!(lam < 0.5)) return fail(h, SHASTA_EINVAL, "dt/dx must be < 1/2");
+  if (nsteps < 0) return fail(h, SHASTA_EINVAL, "nsteps must be >= 0");
+  if (int rc = check_ready(h)) return rc;
+  // layout of the static scratch for the current work tables: records of the
+  // three sweeps, partials, counters and tickets
+  size_t nrec = 0, nfin = 0;
+  for (int ax = 0; ax < 3; ++ax) nrec = std::max(nrec, (size_t)h->n_records[ax]);
+  for (int e = 0; e < h->n_events; ++e) nfin += (size_t)h->evd[e].fin_count;
+  const size_t rec_bytes = align256(sizeof(double) * R_SIZE * nrec);
+  const size_t part_bytes = align256(sizeof(double) * R_SIZE * nfin);
+  const size_t cnt_bytes = align256(sizeof(double) * ((4 + (size_t)h->n_events + 1) / 2));
+  const size_t need = 3 * rec_bytes + part_bytes + cnt_bytes;
+  if (need > kStaticScratchBytes)
+    return fail(h, SHASTA_EINVAL,
+                "shasta_step_noalloc: the step needs " + std::to_string(need) +
+                    " bytes of scratch, the static scratch holds " +
+                    std::to_string(kStaticScratchBytes) +
+                    " (fewer events, or more x windows per work item: shasta_set_tiles)");
+  if (nsteps == 0) return SHASTA_OK;
+  void* base = nullptr;
+  HIPCHECK(h, shasta_launch::static_scratch(&base));
+  char* p = static_cast<char*>(base);
+  StepScratch sc;
+  for (int k = 0; k < 3; ++k) sc.rec[k] = reinterpret_cast<double*>(p + k * rec_bytes);
+  sc.partial = reinterpret_cast<double*>(p + 3 * rec_bytes);
+  sc.cnt = reinterpret_cast<int*>(p + 3 * rec_bytes + part_bytes);
+  sc.may_allocate = false;
+  // queue counters and tickets start at zero (another call may have left
+  // them anywhere); a fill kernel, not a memset, so the call can be captured
+  HIPCHECK(h, shasta_launch::zero(reinterpret_cast<double*>(sc.cnt),
+                                  (int64_t)(cnt_bytes / sizeof(double)), h->stream));
+  for (int s = 0; s < nsteps; ++s) {
+    int parity = h->parity;
+    if (int rc = enqueue_step(h, sc, h->step_index, parity, dt_fm, h->stream)) return rc;
+    h->parity = parity;
+    h->step_index += 1;
   }
   return SHASTA_OK;
 }

@@ -82,6 +82,9 @@ struct Item {
 
 constexpr int kMaxEosNodes = 1024;   // tabled EOS: most nodes
 
+// Bytes of the static device scratch of the step variant that allocates
+// nothing (records, partials, counters and tickets of one handle's step).
+constexpr unsigned long kStaticScratchBytes = 16ul << 20;
 
 struct EosParams {
   int32_t kind;  // 0 ideal, 1 bag, 2 table, 3 baryon-dependent

@@ -21,6 +21,8 @@
 // bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "shasta_internal.hpp"
 #include "shasta_math.hpp"
 #include "shasta_sweeps.hpp"
@@ -316,10 +318,38 @@ __global__ void selftest_kernel(const double* in, double* out, int n, int which)
 
 }  // namespace shasta
 
+// Scratch of the step variant that allocates nothing (shasta_step_noalloc):
+// reduction records, step-reduction partials, queue counters and tickets.
+// One copy per GPU, alive until the process ends; every call on a GPU shares
+// it, so calls that overlap on one GPU race.  Host code never passes this
+// name to a kernel or a copy: it is a host-side stand-in, not the device
+// address, which static_scratch() looks up per device.
+static __device__ __align__(256) unsigned char scratch[shasta::kStaticScratchBytes];
+
 // Entry points used by the host library (C++ linkage, internal).
 namespace shasta_launch {
 using namespace shasta;
 
+// Device address of this device's copy of the static scratch, looked up once
+// per device (with that device current) and kept.
+hipError_t static_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex lock;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 template <int S>
 hipError_t sweep_scheme(int fp32, int axis, const SweepArgs& a, int grid, bool p,

@@ -70,9 +70,12 @@ def test_create_validation(b):
 def test_state_and_eos_validation(b):
     st, h = _create(b, 1, [8, 8, 8])
     assert st == b.OK
-    # step before a workspace is bound
+    # step before a workspace is bound (both forms)
     assert b.shasta_step(h, 0.08, 1) == b.ESTATE
     assert b"workspace" in b.shasta_last_error(h)
+    assert b.shasta_step_noalloc(h, 0.08, 1) == b.ESTATE
+    assert b.shasta_step_noalloc(h, 0.1, 1) == b.EINVAL
+    assert b.shasta_step_noalloc(h, 0.08, -1) == b.EINVAL
     # dt/dx must be in (0, 1/2)
     assert b.shasta_step(h, 0.1, 1) == b.EINVAL
     assert b.shasta_step(h, -0.01, 1) == b.EINVAL
