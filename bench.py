@@ -121,6 +121,36 @@ def copy_ceiling(torch, B, mib=1024, reps=10):
     return 2 * n / (ms * 1e-3) / 1e9
 
 
+def pattern_floor(torch, B, dims, precision, decomposition, reps=10):
+    """Average time of the y and z sweeps' memory pattern without their
+    arithmetic (the library's march copy: same segment length as the
+    decomposition, flattened lanes, same halo rows), timed with HIP events on
+    the current stream; with the algorithmic bytes of a sweep as GB/s."""
+    nx, ny, nz = dims
+    ncell = nx * ny * nz
+    dt = torch.float64 if precision == B.FP64 else torch.float32
+    esize = 8 if precision == B.FP64 else 4
+    src = torch.ones(5 * ncell, dtype=dt, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    out = {}
+    for axis, name in ((1, "sweep_y"), (2, "sweep_z")):
+        seg = int(decomposition.split("/")[axis].split(",")[0]) or dims[axis]
+        for _ in range(3):
+            B.march_copy(src, dst, dims, ncell, axis, seg, precision, st)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            B.march_copy(src, dst, dims, ncell, axis, seg, precision, st)
+        b.record(st)
+        torch.cuda.synchronize()
+        us = 1000.0 * a.elapsed_time(b) / reps
+        out[name] = {"segment": seg, "avg_us": us,
+                     "GBs": ncell * FIELD_PASSES * esize / (us * 1e-6) / 1e9}
+    del src, dst
+    return out
+
+
 def make_state(torch, B, wl, precision):
     dims = wl["dims"] if isinstance(wl["dims"], list) else [wl["dims"]]
     kind, params = wl["eos"]
@@ -373,6 +403,8 @@ def main():
     decomposition = format_tiles(s.decomposition())
     traffic = measured_traffic(dom, args.workload, decomposition)
     copy_gbs = copy_ceiling(torch, B)
+    floor = (pattern_floor(torch, B, wl["dims"], precision, decomposition)
+             if not isinstance(wl["dims"], list) else None)
     step_bytes = 3 * per_launch
     rec = {
         "metric": "SHASTA cell-updates/s per step (FP64 vs FP32 vs batched), % HBM roofline",
@@ -399,7 +431,8 @@ def main():
                      "traffic": traffic, "kernel": dom,
                      "kernel_avg_us": sweeps[dom]["avg_us"],
                      "bytes_per_launch": per_launch,
-                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "pattern_floor": floor},
         "step_hbm_frac": value * (step_bytes / cells) / (HBM_PEAK_GBS * 1e9),
         "kernels": prof,
         "decomposition": decomposition,

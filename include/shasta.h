@@ -274,6 +274,21 @@ int shasta_read_profile(shasta_t* h, double ms[4], int64_t launches[4]);
 int shasta_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
                        void* hip_stream);
 
+/* Copy with the memory pattern of a y (axis 1) or z (axis 2) sweep and none
+ * of its arithmetic, to measure what that pattern alone allows (the march
+ * of the half-step method along the sweep axis, Sec. 3.1).  src_dev and
+ * dst_dev each hold five fields of nx*ny*nz values, x fastest, field q
+ * starting at element q*pitch (pitch >= nx*ny*nz); values are doubles for
+ * SHASTA_FP64 and floats for SHASTA_FP32_MIXED, and one field is below
+ * 2^31 bytes.  One wave per segment of seg_len cells of 64 consecutive
+ * columns of the transverse plane loads rows along the axis one row ahead,
+ * with 6 clamped halo rows before and after the segment, and stores the
+ * segment: afterwards dst_dev holds a copy of src_dev.  Asynchronous on
+ * hip_stream; SHASTA_EINVAL for a bad argument (nothing launched). */
+int shasta_march_copy(const void* src_dev, void* dst_dev, int nx, int ny, int nz,
+                      int64_t pitch, int axis, int seg_len, int precision,
+                      void* hip_stream);
+
 /* Device math self-check: out_dev[i] = f(in_dev[i]) for n values with
  * which = 0: the FP64 reciprocal, 1: the FP64 square root used by the
  * kernels.  Synchronous. */

@@ -60,6 +60,8 @@ _SIGS = {
     "shasta_set_profiling": ([_h, ctypes.c_int], ctypes.c_int),
     "shasta_read_profile": ([_h, _dp, _i64p], ctypes.c_int),
     "shasta_stream_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "shasta_march_copy": ([_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                           ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp], ctypes.c_int),
     "shasta_selftest_math": ([_vp, _vp, ctypes.c_int, ctypes.c_int, _vp], ctypes.c_int),
     "shasta_selftest_recover": ([_h, _vp, _vp, ctypes.c_int], ctypes.c_int),
 }
@@ -256,6 +258,17 @@ def stream_copy(src, dst, nbytes, stream):
                             _vp(stream.cuda_stream))
     if st != OK:
         raise ShastaError(st, "stream copy failed")
+
+
+def march_copy(src, dst, dims, pitch, axis, seg_len, precision, stream):
+    """Copy src to dst (five fields of dims = (nx, ny, nz), field q at
+    element q * pitch) with the memory pattern of the y (axis 1) or z
+    (axis 2) sweep and no arithmetic."""
+    nx, ny, nz = (int(d) for d in dims)
+    st = shasta_march_copy(_vp(src.data_ptr()), _vp(dst.data_ptr()), nx, ny, nz, int(pitch),
+                           int(axis), int(seg_len), int(precision), _vp(stream.cuda_stream))
+    if st != OK:
+        raise ShastaError(st, "march copy failed")
 
 
 def selftest_math(inp, out, which, stream):

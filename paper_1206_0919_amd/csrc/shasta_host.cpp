@@ -36,6 +36,8 @@ hipError_t read(int fp32, EosParams eos, const void* in, int64_t pitch, int64_t 
                 int field, double* dst, hipStream_t st);
 hipError_t zero(double* p, int64_t n, hipStream_t st);
 hipError_t copy(const void* s, void* d, size_t bytes, hipStream_t st);
+hipError_t march_copy(int fp32, const void* s, void* d, int nx, int ny, int nz, int64_t pitch,
+                      int axis, int seg_len, hipStream_t st);
 hipError_t selftest(const double* in, double* out, int n, int which, hipStream_t st);
 hipError_t selftest_recover(EosParams eos, const double* in, double* out, int n,
                             hipStream_t st);
@@ -1282,6 +1284,22 @@ int shasta_read_profile(shasta_t* h, double ms[4], int64_t launches[4]) {
 int shasta_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
   if (!src || !dst || bytes % 16) return SHASTA_EINVAL;
   if (shasta_launch::copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    return SHASTA_EHIP;
+  return SHASTA_OK;
+}
+
+int shasta_march_copy(const void* src, void* dst, int nx, int ny, int nz, int64_t pitch,
+                      int axis, int seg_len, int precision, void* hip_stream) {
+  if (!src || !dst || nx < 1 || ny < 1 || nz < 1 || (axis != 1 && axis != 2) || seg_len < 1 ||
+      (precision != SHASTA_FP64 && precision != SHASTA_FP32_MIXED))
+    return SHASTA_EINVAL;
+  const int64_t ncell = (int64_t)nx * ny * nz;
+  const int64_t elem = precision == SHASTA_FP64 ? 8 : 4;
+  // one field array below 2^31 bytes: 32-bit buffer offsets, as in the sweeps
+  if (pitch < ncell || ncell > 2147483647LL / elem) return SHASTA_EINVAL;
+  if (shasta_launch::march_copy(precision == SHASTA_FP32_MIXED, src, dst, nx, ny, nz, pitch,
+                                axis, seg_len, static_cast<hipStream_t>(hip_stream)) !=
+      hipSuccess)
     return SHASTA_EHIP;
   return SHASTA_OK;
 }

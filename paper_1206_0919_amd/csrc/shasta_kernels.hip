@@ -295,6 +295,63 @@ __global__ __launch_bounds__(256) void stream_copy_kernel(const u32x4* __restric
   }
 }
 
+// Memory pattern of a y or z sweep without its arithmetic (calibration of
+// what that pattern alone allows): one wave per segment of seg_len cells of
+// 64 consecutive columns of the transverse plane (x fastest, the march's
+// default lane layout), blocks mapped to XCDs as the march maps them.  The
+// wave loads the five fields row by row along the axis, one row ahead, from
+// kMarchLag cells before its segment to kMarchLag after it (clamped to the
+// pencil, as the march's halo), and stores its segment's own rows, so dst
+// becomes a copy of src.  Buffer loads and stores are range-checked.
+template <typename T, int AXIS>
+__global__ __launch_bounds__(64) void march_copy_kernel(const T* src, T* dst, int nx, int ny,
+                                                        int nz, int64_t pitch, int seg_len,
+                                                        int ngroups) {
+  const int item = xcd_block();
+  const int grp = item % ngroups, seg = item / ngroups;
+  const int lane = threadIdx.x;
+  const int N = (AXIS == 1) ? ny : nz;
+  const int nb = (AXIS == 1) ? nz : ny;      // rows of the transverse plane
+  const int ncol = nx * nb;
+  const int g = grp * 64 + lane;
+  const bool active = g < ncol;
+  const int gc = min(g, ncol - 1);
+  const int bb = gc / nx, x = gc - bb * nx;
+  const int s_ax = (AXIS == 1) ? nx : nx * ny;
+  const int s_b = (AXIS == 1) ? nx * ny : nx;
+  const int off_col = (x + bb * s_b) * (int)sizeof(T);
+  const int step = s_ax * (int)sizeof(T);
+  const int64_t fbytes = (int64_t)nx * ny * nz * (int64_t)sizeof(T);
+  __amdgpu_buffer_rsrc_t rs[kNF], rd[kNF];
+#pragma unroll
+  for (int q = 0; q < kNF; ++q) {
+    rs[q] = field_rsrc(src + q * pitch, fbytes);
+    rd[q] = field_rsrc(dst + q * pitch, fbytes);
+  }
+  const int s0 = seg * seg_len, s1 = min(N, s0 + seg_len);
+  const int i_lo = s0 - kMarchLag, trips = s1 - s0 + 2 * kMarchLag;
+  T v[2][kNF];
+  auto load = [&](T (&r)[kNF], int i) {
+    const int o = off_col + min(max(i, 0), N - 1) * step;
+#pragma unroll
+    for (int q = 0; q < kNF; ++q) r[q] = buf_load<T>(rs[q], o);
+  };
+  auto store = [&](const T (&r)[kNF], int i) {
+    if (i < s0 || i >= s1) return;
+    const int o = active ? off_col + i * step : kDropOffset;
+#pragma unroll
+    for (int q = 0; q < kNF; ++q) buf_store<T>(rd[q], o, r[q]);
+  };
+  load(v[0], i_lo);
+  for (int t = 0; t < trips; t += 2) {
+    const int i = i_lo + t;
+    load(v[1], i + 1);
+    store(v[0], i);
+    load(v[0], i + 2);
+    store(v[1], i + 1);
+  }
+}
+
 // Recovery self-check: cell i of in = (E, M_x, M_y, M_z, R) -> out =
 // (e, p, |v|, clamped + 2 floored + 4 not converged), through the same recover<EOS>() the
 // sweeps call (|M|^2 summed as M_x^2 + (M_y^2 + M_z^2)).
@@ -471,6 +528,33 @@ hipError_t copy(const void* s, void* d, size_t bytes, hipStream_t st) {
   const int64_t chunk = (n + b - 1) / b;
   hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)b), dim3(256), 0, st,
                      (const u32x4*)s, (u32x4*)d, n, chunk);
+  return hipGetLastError();
+}
+
+hipError_t march_copy(int fp32, const void* s, void* d, int nx, int ny, int nz, int64_t pitch,
+                      int axis, int seg_len, hipStream_t st) {
+  const int N = (axis == 1) ? ny : nz;
+  const int nb = (axis == 1) ? nz : ny;
+  const int64_t ngroups = ((int64_t)nx * nb + 63) / 64;
+  const int64_t blocks = ngroups * ((N + seg_len - 1) / seg_len);
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 g((unsigned)blocks), b(64);
+  const int ng = (int)ngroups;
+  if (fp32) {
+    if (axis == 1)
+      hipLaunchKernelGGL((march_copy_kernel<float, 1>), g, b, 0, st, (const float*)s,
+                         (float*)d, nx, ny, nz, pitch, seg_len, ng);
+    else
+      hipLaunchKernelGGL((march_copy_kernel<float, 2>), g, b, 0, st, (const float*)s,
+                         (float*)d, nx, ny, nz, pitch, seg_len, ng);
+  } else {
+    if (axis == 1)
+      hipLaunchKernelGGL((march_copy_kernel<double, 1>), g, b, 0, st, (const double*)s,
+                         (double*)d, nx, ny, nz, pitch, seg_len, ng);
+    else
+      hipLaunchKernelGGL((march_copy_kernel<double, 2>), g, b, 0, st, (const double*)s,
+                         (double*)d, nx, ny, nz, pitch, seg_len, ng);
+  }
   return hipGetLastError();
 }
 

@@ -130,3 +130,28 @@ def test_state_and_eos_validation(b):
     assert b.shasta_status_str(b.ENONFINITE) == b"non-finite value in the fields"
     assert b.shasta_status_str(b.ENOCONVERGE) == b"recovery did not converge"
     assert b.shasta_forget_tuning() == b.OK
+
+
+def test_march_copy_validation(b):
+    """Every bad argument is refused on the host, before any launch."""
+    p = ctypes.c_void_p(4096)   # never dereferenced: each call below is refused
+    n = 8 * 8 * 8
+    ok = dict(nx=8, ny=8, nz=8, pitch=n, axis=1, seg=4, prec=0)
+
+    def call(src=p, dst=p, **kw):
+        a = dict(ok, **kw)
+        return b.shasta_march_copy(src, dst, a["nx"], a["ny"], a["nz"], a["pitch"], a["axis"],
+                                   a["seg"], a["prec"], None)
+
+    assert call(src=None) == b.EINVAL
+    assert call(dst=None) == b.EINVAL
+    assert call(nx=0) == b.EINVAL
+    assert call(nz=-1) == b.EINVAL
+    assert call(axis=0) == b.EINVAL      # x has no march
+    assert call(axis=3) == b.EINVAL
+    assert call(seg=0) == b.EINVAL
+    assert call(prec=2) == b.EINVAL
+    assert call(pitch=n - 1) == b.EINVAL
+    # one field array below 2^31 bytes
+    assert call(nx=1024, ny=1024, nz=257, pitch=1024 * 1024 * 257) == b.EINVAL
+    assert call(nx=1024, ny=1024, nz=513, pitch=1024 * 1024 * 513, prec=1) == b.EINVAL
