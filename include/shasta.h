@@ -240,11 +240,14 @@ int shasta_set_antidiffusion(shasta_t* h, double diff);
 /* Time candidate decompositions (tiles and persistent or not) on the device
  * with the given dt and keep the fastest per axis.  First pass, per axis: a
  * candidate's time is the fastest of three blocks of reps sweeps of that
- * axis (each reads the current buffer and writes the other one); the six
- * fastest are timed again, interleaved, three more times.  Second pass: the
- * six fastest of each axis are timed in real time steps (three blocks of
+ * axis (each reads the current buffer and writes the other one); the four
+ * fastest and the fastest of up to two further segment lengths (x: windows
+ * per wave) are timed again, interleaved, three more times.  Second pass:
+ * these six of each axis are timed in real time steps (three blocks of
  * reps steps, the other axes at their current choice), and the fastest
- * steps decide.  The state is left as it was: the current fields and the
+ * steps decide; then, for y and for z, the fastest and the fastest of
+ * another segment length are timed in all four pairs, as one sweep's
+ * segments change what the other finds in the caches.  The state is left as it was: the current fields and the
  * accumulators of every event go to host memory (allocated by the call)
  * before the second pass and back after it, with the step index.  The choice
  * is kept, for the rest of the process, under the device, precision, EOS

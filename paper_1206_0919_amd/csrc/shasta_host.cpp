@@ -1094,8 +1094,9 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
   int rc = SHASTA_OK;
   // first pass, per axis: every candidate decomposition (x: windows per
   // wave; y/z: segment length and lanes along x; persistent launch or not)
-  // timed on repeated sweeps of that axis alone; then the six fastest again,
-  // interleaved, three more times (a candidate keeps its fastest time)
+  // timed on repeated sweeps of that axis alone; then six of them again
+  // (below), interleaved, three more times (a candidate keeps its fastest
+  // time)
   std::vector<TuneChoice> ranked[3];
   for (int ax = 0; ax < 3 && rc == SHASTA_OK; ++ax) {
     std::vector<TuneChoice> cands;
@@ -1124,25 +1125,34 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
     if (rc) break;
     std::stable_sort(cands.begin(), cands.end(),
                      [](const TuneChoice& x, const TuneChoice& y) { return x.ms < y.ms; });
-    const size_t top = std::min<size_t>(6, cands.size());
+    // the four fastest, then the fastest of up to two further segment
+    // lengths (windows per wave for x): a sweep timed alone favours long
+    // segments that the full step does not (256^3 FP32: whole pencils for y
+    // at 200-206 us in the step against 184 us for 128-cell segments)
+    std::vector<TuneChoice> sel(cands.begin(), cands.begin() + std::min<size_t>(4, cands.size()));
+    for (const TuneChoice& c : cands) {
+      if (sel.size() >= 6) break;
+      bool fresh = true;
+      for (const TuneChoice& t : sel) fresh = fresh && t.p0 != c.p0;
+      if (fresh) sel.push_back(c);
+    }
     for (int round = 0; round < 3 && rc == SHASTA_OK; ++round)
-      for (size_t i = 0; i < top; ++i) {
+      for (TuneChoice& c : sel) {
         float ms;
-        if ((rc = apply(ax, cands[i]))) break;
+        if ((rc = apply(ax, c))) break;
         if ((rc = time_sweeps(one, 1, ms))) break;
-        report("sweep-again", ax, cands[i], ms);
-        cands[i].ms = std::min(cands[i].ms, ms);
+        report("sweep-again", ax, c, ms);
+        c.ms = std::min(c.ms, ms);
       }
     if (rc) break;
-    std::stable_sort(cands.begin(), cands.begin() + top,
+    std::stable_sort(sel.begin(), sel.end(),
                      [](const TuneChoice& x, const TuneChoice& y) { return x.ms < y.ms; });
-    cands.resize(top);
-    ranked[ax] = cands;
-    set_choice(h, ax, cands[0]);
+    ranked[ax] = sel;
+    set_choice(h, ax, sel[0]);
   }
   // second pass: a sweep alone, repeated on the same input, does not see
   // what the step's other sweeps leave in the caches, nor their order of
-  // reading and writing.  The six fastest of each axis are timed again in
+  // reading and writing.  The six kept for each axis are timed again in
   // real time steps (the other axes at their current choice), and the
   // fastest step wins.  The steps advance the state, so the current buffer
   // of every event, its accumulators, the step index and the buffer parity
@@ -1198,6 +1208,7 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
       return SHASTA_OK;
     };
     rc = copy_state(false);
+    std::vector<TuneChoice> by_step[3];   // per axis, fastest step first
     for (int ax = 0; ax < 3 && rc == SHASTA_OK; ++ax) {
       const size_t n = std::min<size_t>(6, ranked[ax].size());
       std::vector<float> best(n, 1e30f);
@@ -1210,8 +1221,45 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
           best[i] = std::min(best[i], ms);
         }
       if (rc) break;
-      const size_t w = std::min_element(best.begin(), best.end()) - best.begin();
-      set_choice(h, ax, ranked[ax][w]);
+      for (size_t i = 0; i < n; ++i) ranked[ax][i].ms = best[i];
+      by_step[ax].assign(ranked[ax].begin(), ranked[ax].begin() + n);
+      std::stable_sort(by_step[ax].begin(), by_step[ax].end(),
+                       [](const TuneChoice& x, const TuneChoice& y) { return x.ms < y.ms; });
+      set_choice(h, ax, by_step[ax][0]);
+    }
+    // third pass: what one of the y/z sweeps finds in the caches depends on
+    // how the other one walked the grid (256^3 FP32: y and z both in
+    // 128-cell segments 0.581 ms per step, either one alone 0.605, both whole
+    // pencils 0.610), which the axis-by-axis passes cannot see.  For y and
+    // for z the fastest candidate and the fastest of another segment length
+    // are timed in all four pairs.
+    if (rc == SHASTA_OK && by_step[1].size() >= 2 && by_step[2].size() >= 2) {
+      TuneChoice two[3][2];
+      for (int ax = 1; ax < 3; ++ax) {
+        two[ax][0] = by_step[ax][0];
+        two[ax][1] = by_step[ax][1];
+        for (const TuneChoice& c : by_step[ax])
+          if (c.p0 != by_step[ax][0].p0) { two[ax][1] = c; break; }
+      }
+      float best = 1e30f;
+      int by = 0, bz = 0;
+      for (int round = 0; round < 2 && rc == SHASTA_OK; ++round)
+        for (int iy = 0; iy < 2 && rc == SHASTA_OK; ++iy)
+          for (int iz = 0; iz < 2; ++iz) {
+            float ms;
+            set_choice(h, 1, two[1][iy]);
+            if ((rc = apply(2, two[2][iz]))) break;
+            if ((rc = time_steps(ms))) break;
+            if (log)
+              std::fprintf(stderr, "shasta_autotune pair y %d,%d,%d z %d,%d,%d: %.4f ms\n",
+                           two[1][iy].p0, two[1][iy].p1, two[1][iy].pers ? 1 : 0,
+                           two[2][iz].p0, two[2][iz].p1, two[2][iz].pers ? 1 : 0, ms);
+            if (ms < best) { best = ms; by = iy; bz = iz; }
+          }
+      if (rc == SHASTA_OK) {
+        set_choice(h, 1, two[1][by]);
+        set_choice(h, 2, two[2][bz]);
+      }
     }
     h->parity = parity0;
     h->step_index = step0;

@@ -148,6 +148,17 @@ def crossover_eos_table(n_nodes=48, B=None, e_c=1.0, width=1.0, e_max=1.0e3):
     return e, p
 
 
+def steep_eos_table():
+    """A causal table whose segments alternate soft and stiff slopes, up to
+    dp/de = 3/4 (nodes in GeV/fm^3): the steepest EOS on which the
+    recovery's fixed point is pinned to converge at the guard's largest
+    |M|/E."""
+    e = np.array([0.0, 0.5, 2.0, 10.0, 100.0, 1000.0])
+    slopes = np.array([0.2, 0.75, 0.1, 0.75, 1.0 / 3.0])
+    p = np.concatenate([[0.0], np.cumsum(slopes * np.diff(e))])
+    return e, p
+
+
 def bag_eos_table(B, e_H, e_top=1.0e3):
     """The bag model of bag_parameters() as a table: its break points e_H and
     e_Q = e_H + 4B plus one node far in the plasma phase (the last segment,
