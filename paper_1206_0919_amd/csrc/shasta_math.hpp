@@ -48,6 +48,24 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return __builtin_fma(d, h, g);
 }
 
+// The same with one refinement step less, for recoveries whose results are
+// rounded to FP32 (the sweeps of FP32 fields): the reciprocal within about
+// 20 ulp and the root within about 40 ulp of FP64, some 1e-7 of an FP32 ulp.
+template <bool kFast>
+__device__ __forceinline__ double rcp_r(double x) {
+  if constexpr (!kFast) return rcp(x);
+  const double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+template <bool kFast>
+__device__ __forceinline__ double sqrt_r(double x) {
+  if constexpr (!kFast) return sqrt_pos(x);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double g = x * y;
+  const double r = __builtin_fma(-g, 0.5 * y, 0.5);
+  return __builtin_fma(g, r, g);
+}
+
 // True if any lane of the wave has pred set (a wave-uniform branch lets the
 // rare paths below cost nothing when no lane takes them).
 __device__ __forceinline__ bool any_lane(bool pred) {
@@ -79,11 +97,12 @@ struct Recovered {
 };
 
 // w = v/|M_c| and e for p = e/3, on (E, M^2) of moderate size.
+template <bool kFast = false>
 __device__ __forceinline__ void ideal_root(double E, double M2, double& w,
                                            double& e) {
   // v = 3 M / (2 E + sqrt(4 E^2 - 3 M^2)),  e = E - M v
-  const double s = sqrt_pos(__builtin_fma(4.0 * E, E, -3.0 * M2));
-  w = 3.0 * rcp(__builtin_fma(2.0, E, s));
+  const double s = sqrt_r<kFast>(__builtin_fma(4.0 * E, E, -3.0 * M2));
+  w = 3.0 * rcp_r<kFast>(__builtin_fma(2.0, E, s));
   e = __builtin_fma(-M2, w, E);
 }
 
@@ -110,11 +129,12 @@ __device__ __forceinline__ void ideal_root_scaled(double E, double M2, bool clam
 // Root of a linear EOS branch p = a e + b (a >= 0): w = v/|M| and e.  The
 // root is homogeneous of degree 0 in (E, M, b) for w E, so the squares are
 // kept in the normal range by a power-of-two scaling of all three.
+template <bool kFast = false>
 __device__ __forceinline__ void linear_root(double a, double b, double E, double M2,
                                             double& w, double& e) {
   const double K = __builtin_fma(1.0 + a, E, b);
   const double disc = fmax(__builtin_fma(K, K, -4.0 * a * M2), 0.0);
-  w = 2.0 * rcp(K + sqrt_pos(disc));
+  w = 2.0 * rcp_r<kFast>(K + sqrt_r<kFast>(disc));
   e = __builtin_fma(-M2, w, E);
 }
 __device__ __forceinline__ void linear_root_scaled(double a, double b, double E, double M2,
@@ -203,8 +223,9 @@ __device__ __forceinline__ double table_pressure(const EosParams& eos, double e)
 // EOS: 0 = ideal gas p = e/3, 1 = bag model, 2 = tabled p(e), linear between
 // nodes, 3 = baryon-dependent p(e, n) (compile-time, as the paper specialises
 // its kernels per EOS instead of branching at run time).  R, the fifth
-// conserved field, is used by EOS 3 only.
-template <int EOS>
+// conserved field, is used by EOS 3 only.  kFast: results rounded to FP32
+// afterwards, one refinement step less in the common path (rcp_r, sqrt_r).
+template <int EOS, bool kFast = false>
 __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
                                              double Mpar, double Mt1,
                                              double Mt2, double R) {
@@ -224,7 +245,7 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
   double ta = 0.0, tb = 0.0;   // tabled EOS: the segment's p = ta e + tb
   if constexpr (EOS == 0) {
     rare = !(Ec > 1e-140 && Ec < 1e140);
-    ideal_root(Ec, M2c, w, e);
+    ideal_root<kFast>(Ec, M2c, w, e);
   } else if constexpr (EOS == 3) {
     rare = false;   // the solve is scaled by construction
     r.noconv = baryon_root(eos.cs2, eos.mass * R, Ec, M2, r.clamped, eos.newton_max, w, e,
@@ -246,7 +267,7 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
     ta = eos.tab[2 * m + k];
     tb = eos.tab[3 * m + k];
     rare = !(Ec > 1e-140 && Ec < 1e140);
-    linear_root(ta, tb, Ec, M2c, w, e);
+    linear_root<kFast>(ta, tb, Ec, M2c, w, e);
     r.p = __builtin_fma(ta, e, tb);
   } else {
     // bag model: the recovery function v (E + p(E - M v)) - M increases with
@@ -261,9 +282,9 @@ __device__ __forceinline__ Recovered recover(const EosParams& eos, double E,
     const double b = qgp ? -(4.0 * kThird) * eos.B : 0.0;
     const double K = __builtin_fma(4.0 * kThird, Ec, b);
     const double dq =
-        0.5 * (K + sqrt_pos(__builtin_fma(K, K, -(4.0 * kThird) * M2c)));
+        0.5 * (K + sqrt_r<kFast>(__builtin_fma(K, K, -(4.0 * kThird) * M2c)));
     const double den = mixed ? (Ec + pc) : dq;
-    w = rcp(den);
+    w = rcp_r<kFast>(den);
     e = __builtin_fma(-M2c, w, Ec);
     r.p = mixed ? pc : __builtin_fma(kThird, e, b);
     rare = hadron && !(Ec > 1e-140);

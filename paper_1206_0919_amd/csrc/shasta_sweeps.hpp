@@ -232,7 +232,7 @@ struct MarchP : MarchCommon<T, AXIS, EOS> {
 #pragma unroll
     for (int q = 0; q < kNF; ++q) L.un[uslot][q][this->lane] = u[q][S0];
     {
-      const Recovered r = recover<eos_of<EOS>>(*this->eos, double(u[0][S0]), double(u[QP][S0]),
+      const Recovered r = recover<eos_of<EOS>, sizeof(T) == 4>(*this->eos, double(u[0][S0]), double(u[QP][S0]),
                                        double(u[QT1][S0]), double(u[QT2][S0]),
                                        double(u[4][S0]));
       const double v = r.w * double(u[QP][S0]);
@@ -324,7 +324,7 @@ struct MarchC : MarchCommon<T, AXIS, EOS> {
     } else if (EDGE && k >= N) {
       ec[S3] = ec[S4]; fE[S3] = fE[S4]; fM[S3] = fM[S4];
     } else {
-      const Recovered r = recover<eos_of<EOS>>(*this->eos, double(uh[0]), double(uh[QP]),
+      const Recovered r = recover<eos_of<EOS>, sizeof(T) == 4>(*this->eos, double(uh[0]), double(uh[QP]),
                                        double(uh[QT1]), double(uh[QT2]), double(uh[4]));
       const double v = r.w * double(uh[QP]);
       ec[S3] = T(this->lam * v);
@@ -804,7 +804,7 @@ void sweep_x(SweepArgs A) {
       T ep[kXCells], fE[kXCells], fM[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered r = recover<eos_of<EOS>>(A.eos, double(u[0][j]), double(u[QP][j]),
+        const Recovered r = recover<eos_of<EOS>, sizeof(T) == 4>(A.eos, double(u[0][j]), double(u[QP][j]),
                                          double(u[QT1][j]), double(u[QT2][j]),
                                          double(u[4][j]));
         const double v = r.w * double(u[QP][j]);
@@ -835,7 +835,7 @@ void sweep_x(SweepArgs A) {
       T ec[kXCells], fEc[kXCells], fMc[kXCells];
 #pragma unroll
       for (int j = 0; j < kXCells; ++j) {
-        const Recovered r = recover<eos_of<EOS>>(A.eos, double(uh[0][j]), double(uh[QP][j]),
+        const Recovered r = recover<eos_of<EOS>, sizeof(T) == 4>(A.eos, double(uh[0][j]), double(uh[QP][j]),
                                          double(uh[QT1][j]), double(uh[QT2][j]),
                                          double(uh[4][j]));
         const double v = r.w * double(uh[QP][j]);
