@@ -1127,8 +1127,7 @@ int shasta_autotune(shasta_t* h, double dt_fm, int reps) {
                      [](const TuneChoice& x, const TuneChoice& y) { return x.ms < y.ms; });
     // the four fastest, then the fastest of up to two further segment
     // lengths (windows per wave for x): a sweep timed alone favours long
-    // segments that the full step does not (256^3 FP32: whole pencils for y
-    // at 200-206 us in the step against 184 us for 128-cell segments)
+    // segments, which in the full step are not always faster
     std::vector<TuneChoice> sel(cands.begin(), cands.begin() + std::min<size_t>(4, cands.size()));
     for (const TuneChoice& c : cands) {
       if (sel.size() >= 6) break;
