@@ -432,7 +432,11 @@ def main():
                      "kernel_avg_us": sweeps[dom]["avg_us"],
                      "bytes_per_launch": per_launch,
                      "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                     "pattern_floor": floor},
+                     "pattern_floor": floor,
+                     # the dominant kernel's time against the copy with its own
+                     # memory pattern and no arithmetic (y and z sweeps only)
+                     "frac_of_pattern": (floor[dom]["avg_us"] / sweeps[dom]["avg_us"]
+                                         if floor and dom in floor else None)},
         "step_hbm_frac": value * (step_bytes / cells) / (HBM_PEAK_GBS * 1e9),
         "kernels": prof,
         "decomposition": decomposition,
