@@ -1,6 +1,6 @@
 """Host-side logic of bench.py (no GPU): the kernel-source hash that ties a
-committed counter summary to the code it was measured on, and the matching
-of a summary to a decomposition."""
+committed counter summary to the code it was measured on, the matching of a
+summary to a decomposition, and the refusal of more than one GPU."""
 import json
 import os
 import sys
@@ -59,3 +59,13 @@ def test_measured_traffic_matches_hash_and_decomposition(tmp_path, monkeypatch):
     assert bench.measured_traffic("sweep_x", "other", "8,0,0/1,1,1/1,1,1") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.measured_traffic("sweep_x", "w", "8,0,0/1,1,1/1,1,1") is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU is in scope: the benchmark says so and exits before any GPU work
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
