@@ -278,8 +278,9 @@ int shasta_stream_copy(const void* src_dev, void* dst_dev, size_t bytes,
                        void* hip_stream);
 
 /* Copy with the memory pattern of a y (axis 1) or z (axis 2) sweep and none
- * of its arithmetic, to measure what that pattern alone allows (the march
- * of the half-step method along the sweep axis, Sec. 3.1).  src_dev and
+ * of its arithmetic, to measure what that pattern alone allows (a
+ * calibration helper like shasta_stream_copy; the sweep it mimics reads its
+ * pencils with the 3-cell halos of both half steps, Sec. 3.1).  src_dev and
  * dst_dev each hold five fields of nx*ny*nz values, x fastest, field q
  * starting at element q*pitch (pitch >= nx*ny*nz); values are doubles for
  * SHASTA_FP64 and floats for SHASTA_FP32_MIXED, and one field is below
