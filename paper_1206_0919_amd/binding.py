@@ -253,7 +253,17 @@ def forget_tuning():
     _check(None, shasta_forget_tuning())
 
 
+def _check_device_buffers(nbytes, *tensors):
+    for t in tensors:
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("device buffers must be contiguous GPU tensors")
+        if t.numel() * t.element_size() < nbytes:
+            raise ValueError(f"buffer of {t.numel() * t.element_size()} bytes, "
+                             f"the copy needs {nbytes}")
+
+
 def stream_copy(src, dst, nbytes, stream):
+    _check_device_buffers(int(nbytes), src, dst)
     st = shasta_stream_copy(_vp(src.data_ptr()), _vp(dst.data_ptr()), int(nbytes),
                             _vp(stream.cuda_stream))
     if st != OK:
@@ -265,6 +275,9 @@ def march_copy(src, dst, dims, pitch, axis, seg_len, precision, stream):
     element q * pitch) with the memory pattern of the y (axis 1) or z
     (axis 2) sweep and no arithmetic."""
     nx, ny, nz = (int(d) for d in dims)
+    if src.dtype != dst.dtype or (precision == FP64) != (src.element_size() == 8):
+        raise ValueError("march copy: float64 buffers for FP64, float32 for FP32_MIXED")
+    _check_device_buffers((4 * int(pitch) + nx * ny * nz) * src.element_size(), src, dst)
     st = shasta_march_copy(_vp(src.data_ptr()), _vp(dst.data_ptr()), nx, ny, nz, int(pitch),
                            int(axis), int(seg_len), int(precision), _vp(stream.cuda_stream))
     if st != OK:

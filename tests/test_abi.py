@@ -155,3 +155,16 @@ def test_march_copy_validation(b):
     # one field array below 2^31 bytes
     assert call(nx=1024, ny=1024, nz=257, pitch=1024 * 1024 * 257) == b.EINVAL
     assert call(nx=1024, ny=1024, nz=513, pitch=1024 * 1024 * 513, prec=1) == b.EINVAL
+
+
+def test_copy_bindings_check_their_buffers(b):
+    # host tensors, short buffers and a wrong element type are refused before
+    # any call reaches the library
+    import torch
+    x = torch.zeros(64, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        b.stream_copy(x, x, 64, None)
+    with pytest.raises(ValueError):
+        b.march_copy(x, x, (2, 2, 2), 8, 1, 4, b.FP64, None)
+    with pytest.raises(ValueError):
+        b.march_copy(x.float(), x.float(), (2, 2, 2), 8, 1, 4, b.FP64, None)
